@@ -1,0 +1,95 @@
+"""Seeded synthetic inputs shared by the oracle-side and GPU-side tests and by
+bench.py.  Holds no arithmetic of the transform itself: only random numbers
+with the shapes and distributions of the workloads.
+
+The paper measures on seeded random data only (uniform coefficients, points
+uniform in balls, Section 8); the workloads below keep that structure at the
+sizes used for parity tests and for the throughput measurement.
+"""
+import numpy as np
+
+
+def num_coeffs(B):
+    return B * (B + 1) * (2 * B + 1) // 6
+
+
+def degree_n(B):
+    """The first index n of every coefficient, in coefficient order (n outer)."""
+    return np.concatenate([np.full(n * n, n, dtype=np.int64) for n in range(1, B + 1)])
+
+
+def coefficients(B, seed, decay=1.5):
+    """Re, Im iid N(0,1), scaled by n^-decay."""
+    rng = np.random.default_rng(seed)
+    nc = num_coeffs(B)
+    c = rng.standard_normal(nc) + 1j * rng.standard_normal(nc)
+    return c * degree_n(B).astype(np.float64) ** (-decay)
+
+
+def coefficients_uniform(B, seed):
+    """Re, Im iid U[-1, 1] (the coefficient distribution of Section 8)."""
+    rng = np.random.default_rng(seed)
+    nc = num_coeffs(B)
+    return rng.uniform(-1, 1, nc) + 1j * rng.uniform(-1, 1, nc)
+
+
+def gaussian_points(M, seed):
+    """Points iid N(0, I/2): density proportional to exp(-r^2), the weight of H."""
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((M, 3)) * np.sqrt(0.5)
+
+
+def ball_points(M, radius, seed):
+    """Points uniform in the ball of the given radius (Section 8)."""
+    rng = np.random.default_rng(seed)
+    d = rng.standard_normal((M, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    r = radius * rng.uniform(0, 1, M) ** (1.0 / 3.0)
+    return d * r[:, None]
+
+
+def mixed_points(M, seed, frac_ball=0.1, radius=4.0):
+    """(1 - frac_ball) M Gaussian points plus frac_ball M uniform in a ball."""
+    mb = int(round(M * frac_ball))
+    g = gaussian_points(M - mb, seed)
+    b = ball_points(mb, radius, seed + 1)
+    return np.concatenate([g, b], axis=0)
+
+
+def samples(M, seed):
+    """Adjoint input y: iid complex N(0, 1)."""
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(M) + 1j * rng.standard_normal(M)
+
+
+# Workloads: name -> (B, M, point generator, coefficient decay, sigma, q, precision)
+WORKLOADS = {
+    # FP64 forward + adjoint at B=8, M=1e4 Gaussian points, n^-2 decay; q = 16 as in Section 8.
+    "b8_m1e4_f64": dict(B=8, M=10_000, points="gaussian", decay=2.0, sigma=2, q=16, prec="f64"),
+    # B=32, M=1e6 (0.9e6 Gaussian + 0.1e6 uniform in the ball r <= 4), n^-1.5, q=6.
+    "b32_m1e6_f64": dict(B=32, M=1_000_000, points="mixed", decay=1.5, sigma=2, q=6, prec="f64"),
+    "b32_m1e6_f32": dict(B=32, M=1_000_000, points="mixed", decay=1.5, sigma=2, q=6, prec="f32"),
+    # Throughput workload: B=64, M=4e6 Gaussian points, n^-1.5, FP32, q=6.
+    "b64_m4e6_f32": dict(B=64, M=4_000_000, points="gaussian", decay=1.5, sigma=2, q=6, prec="f32"),
+    "b64_m4e6_f64": dict(B=64, M=4_000_000, points="gaussian", decay=1.5, sigma=2, q=6, prec="f64"),
+}
+
+
+def make_points(kind, M, seed):
+    if kind == "gaussian":
+        return gaussian_points(M, seed)
+    if kind == "mixed":
+        return mixed_points(M, seed)
+    if kind.startswith("ball"):
+        return ball_points(M, float(kind[4:]), seed)
+    raise ValueError(kind)
+
+
+def workload(name, seed=0, M=None):
+    w = dict(WORKLOADS[name])
+    if M is not None:
+        w["M"] = M
+    pts = make_points(w["points"], w["M"], seed)
+    fhat = coefficients(w["B"], seed + 100, w["decay"])
+    y = samples(w["M"], seed + 200)
+    return w, pts, fhat, y
