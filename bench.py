@@ -1,0 +1,216 @@
+"""Throughput of the fast SGL Fourier transform for scattered data on one MI355X.
+
+One step = one forward (f = Lambda fhat) plus one adjoint (fhat = Lambda^H y)
+over the whole workload, inputs resident in HBM.  Default workload: B=64,
+M=4e6 points iid N(0, I/2), coefficients with n^-1.5 decay, FP32, sigma=2,
+q=6.  Prints one JSON line with points/s, the roofline position of the
+dominant kernel (HIP-event time on the plan's stream), the accuracy against
+the direct-sum oracle on a sampled subset, and the oracle's own CPU rate.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "scattered points/s fwd+adj at B=64, M=4e6, rel err≤1e-5; frac of HBM roofline"
+
+# MI355X published peaks
+HBM_PEAK_GBS = 8000.0
+# FP32 vector FMA issue rate without packed math: 256 CU x 4 SIMD x 16 lanes x
+# 2 flop x 2.4 GHz (the build disables packed FP32 instructions).
+ALU_PEAK_F32_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+ALU_PEAK_F64_TFLOPS = 78.6
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="b64_m4e6_f32")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--check-points", type=int, default=2000)
+    return ap.parse_args()
+
+
+def spread_flops(q):
+    """Algorithmic flops per point of the windowed gather (or scatter): (2q)^3
+    complex-by-real multiply-adds (4 flop) for the separable sum."""
+    t = 2 * q
+    return 4 * (t ** 3 + t ** 2 + t)
+
+
+def fft_bytes(info, B, cb):
+    """Algorithmic HBM bytes of one 3D FFT (three pruned passes): each pass reads
+    its nonzero input rows once and writes its needed output rows once."""
+    n0, n1, n2 = 4 * B, 2 * B, 2 * B
+    N2, E0, E1 = info["N2"], info["E0"], info["E1"]
+    a = n0 * n1 * n2 + n0 * n1 * N2
+    b = n0 * n1 * N2 + n0 * E1 * N2
+    c = n0 * E1 * N2 + E0 * E1 * N2
+    return {"fft_A": a * cb, "fft_B": b * cb, "fft_C": c * cb, "fft_Ah": a * cb, "fft_Bh": b * cb, "fft_Ch": c * cb}
+
+
+def cpu_baseline(B, pts, fh, y, seconds):
+    """The oracle as it stands (direct O(B^3) sum per point, OpenMP), forward +
+    adjoint on a bounded sample of the same workload."""
+    import oracle
+
+    threads = oracle.max_threads()
+    m0 = 500
+    t = time.perf_counter()
+    oracle.direct_forward(B, pts[:m0], fh)
+    oracle.direct_adjoint(B, pts[:m0], y[:m0])
+    dt = time.perf_counter() - t
+    m = int(min(len(pts), max(m0, m0 * seconds / max(dt, 1e-6))))
+    t = time.perf_counter()
+    oracle.direct_forward(B, pts[:m], fh)
+    oracle.direct_adjoint(B, pts[:m], y[:m])
+    dt = time.perf_counter() - t
+    return {"value": m / dt, "unit": "points/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {m} of the {len(pts)} workload points, forward + adjoint, {dt:.1f} s"}
+
+
+def accuracy(B, plan, pts_used, fh_used, f_gpu, y, prec, m, torch, cdt):
+    """Relative l2/linf error against the direct sum on m sampled points
+    (forward) and for the adjoint of samples supported on those points."""
+    import oracle
+
+    rng = np.random.default_rng(12345)
+    idx = np.sort(rng.choice(len(pts_used), m, replace=False))
+    f0 = oracle.direct_forward(B, pts_used[idx], fh_used)
+    fs = f_gpu[idx]
+    ys = np.zeros(len(pts_used), dtype=np.complex128)
+    ys[idx] = y[idx]
+    if prec == "f32":
+        ys = ys.astype(np.complex64).astype(np.complex128)
+    g = plan.adjoint(torch.from_numpy(ys).to("cuda", cdt))
+    torch.cuda.synchronize()
+    g = g.cpu().numpy().astype(np.complex128)
+    g0 = oracle.direct_adjoint(B, pts_used[idx], ys[idx])
+    n2 = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    ni = lambda a, b: float(np.abs(a - b).max() / np.abs(b).max())
+    return {"fwd_rel_l2": n2(fs, f0), "fwd_rel_linf": ni(fs, f0), "adj_rel_l2": n2(g, g0),
+            "adj_rel_linf": ni(g, g0), "sample_points": m}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported by this build "
+              "(the transform shards over points, see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from tests import workloads as wl
+    import paper_1809_10786_amd as sgl
+
+    w, pts, fh, y = wl.workload(a.workload, seed=0)
+    B, M, q, prec = w["B"], w["M"], w["q"], w["prec"]
+    rdt = torch.float64 if prec == "f64" else torch.float32
+    cdt = torch.complex128 if prec == "f64" else torch.complex64
+    cb = 16 if prec == "f64" else 8
+    print(f"[bench] workload {a.workload}: B={B} M={M} q={q} {prec}", file=sys.stderr, flush=True)
+
+    dpts = torch.from_numpy(pts).to("cuda", rdt)
+    dfh = torch.from_numpy(fh).to("cuda", cdt)
+    dy = torch.from_numpy(y).to("cuda", cdt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = sgl.Plan(dpts, B, sigma=w["sigma"], q=q, precision=prec)
+    torch.cuda.synchronize()
+    plan_ms = (time.perf_counter() - t0) * 1e3
+    info = plan.info()
+    print(f"[bench] plan {plan_ms:.1f} ms, rho={plan.rho:.4f}, info={info}", file=sys.stderr, flush=True)
+
+    f = torch.empty(M, dtype=cdt, device="cuda")
+    g = torch.empty(plan.nc, dtype=cdt, device="cuda")
+    for _ in range(a.warmup):
+        plan.forward(dfh, out=f)
+        plan.adjoint(dy, out=g)
+    torch.cuda.synchronize()
+    print("[bench] warmup done", file=sys.stderr, flush=True)
+
+    plan.profile(True)
+    plan.stage_times(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        plan.forward(dfh, out=f)
+        plan.adjoint(dy, out=g)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    stages = plan.stage_times(reset=True)
+    plan.profile(False)
+    ms_per_step = elapsed * 1e3 / a.steps
+    value = M / (ms_per_step / 1e3)
+    print(f"[bench] {a.steps} steps: {ms_per_step:.3f} ms/step, {value:.4g} points/s", file=sys.stderr, flush=True)
+
+    # per-stage averages and the dominant kernel's roofline position
+    avg = {k: v[0] / v[1] for k, v in stages.items()}
+    dom = max(avg, key=avg.get)
+    fb = fft_bytes(info, B, cb)
+    if dom in ("gather", "scatter"):
+        flops = spread_flops(q) * M
+        peak = ALU_PEAK_F32_TFLOPS if prec == "f32" else ALU_PEAK_F64_TFLOPS
+        achieved = flops / (avg[dom] * 1e-3) / 1e12
+        roof = {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                "frac": achieved / peak, "traffic": None}
+    else:
+        byts = fb.get(dom, 0)
+        achieved = byts / (avg[dom] * 1e-3) / 1e9
+        roof = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None}
+    # HBM fraction of the whole step at algorithmic bytes
+    step_bytes = sum(fb.values()) + 2 * M * (cb + 16 + 4)
+    hbm_frac_step = step_bytes / (ms_per_step * 1e-3) / (HBM_PEAK_GBS * 1e9)
+    print(f"[bench] stages (ms/launch): " + ", ".join(f"{k}={v:.4f}" for k, v in avg.items()), file=sys.stderr,
+          flush=True)
+
+    f_host = f.cpu().numpy().astype(np.complex128)
+    pts_used = pts.astype(np.float32).astype(np.float64) if prec == "f32" else pts
+    fh_used = fh.astype(np.complex64).astype(np.complex128) if prec == "f32" else fh
+    acc = accuracy(B, plan, pts_used, fh_used, f_host, y, prec, a.check_points, torch, cdt)
+    print(f"[bench] accuracy {acc}", file=sys.stderr, flush=True)
+
+    cpu = None
+    if not a.no_cpu_baseline:
+        cpu = cpu_baseline(B, pts_used, fh_used, y.astype(np.complex128), a.cpu_seconds)
+        print(f"[bench] cpu baseline {cpu}", file=sys.stderr, flush=True)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": prec,
+        "data": "synthetic",
+        "config": {"workload": a.workload, "B": B, "M": M, "sigma": w["sigma"], "q": q,
+                   "points": w["points"], "coeff_decay": w["decay"], "rho": plan.rho},
+        "roofline": roof,
+        "hbm_frac_step": hbm_frac_step,
+        "cpu_baseline": cpu,
+        "rel_err": acc,
+        "stages_ms": {k: round(v, 5) for k, v in avg.items()},
+        "plan_ms": plan_ms,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

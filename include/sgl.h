@@ -1,0 +1,176 @@
+/*
+ * sgl.h -- fast SGL Fourier transform for scattered data (NFSGLFT) and its
+ * adjoint on AMD Instinct MI355X (gfx950).
+ *
+ * Problem statement (Wuelker, "Fast SGL Fourier transforms for scattered
+ * data", Def. 1.3 and eq. (1.2)): for M points x_i in R^3 and bandwidth B,
+ *     f = Lambda fhat,   Lambda[i, mu] = H_{n(mu) l(mu) m(mu)}(x_i),
+ * with the SGL basis functions H_nlm of Def. 1.1 and the coefficient order
+ * mu = n(n-1)(2n-1)/6 + l(l+1) + m (Section 1).  The adjoint is Lambda^H
+ * (Section 1, the paragraph after eq. (1.3)).  Both are computed by the fast
+ * algorithm of Section 6 (Thm. 6.2, Cor. 6.3): a radial and a polar
+ * conversion into the coefficients eta of a 3D trigonometric polynomial
+ * (eq. nfsglft_nfft) on the 4B x 2B x 2B grid of Remark 8.1, followed by the
+ * Gaussian-window NFFT of Section 2 on the oversampled grid sigma*n.  Only
+ * the NFFT is approximate (Section 7); its error falls at least
+ * exponentially in the cutoff q (Thm. 2.7).
+ *
+ * Conventions shared by every entry point
+ *  - Memory: all data pointers are DEVICE pointers owned by the caller; the
+ *    library never frees them.  A plan owns its tables and workspace.
+ *  - Complex data are interleaved (re, im): double2 for SGL_F64, float2 for
+ *    SGL_F32 (the layout of torch.complex128 / torch.complex64).
+ *  - Points are Cartesian (x, y, z) rows, M x 3, double for SGL_F64 and
+ *    float for SGL_F32.  The point transform itself always runs in FP64.
+ *  - Streams: every call enqueues on the plan's stream and returns without a
+ *    host synchronisation, except sgl_plan, which is synchronous.
+ *  - Errors: status codes only, nothing is thrown across the ABI.  Argument
+ *    checks run on the host before any work is enqueued; on error, outputs
+ *    are unspecified and nothing has been written to them.  Inputs and
+ *    outputs must not overlap (SGL_E_INVAL).  A plan must not be used from
+ *    two host threads at once.
+ */
+#ifndef SGL_H
+#define SGL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sgl_plan_s *sgl_plan_t;
+
+typedef enum {
+  SGL_OK = 0,
+  SGL_E_INVAL = -1,       /* bad argument, null pointer, aliasing, non-finite point */
+  SGL_E_RANGE = -2,       /* user rho smaller than max_i |x_i|                      */
+  SGL_E_NOMEM = -3,       /* device or host allocation failed                       */
+  SGL_E_DEVICE = -4,      /* HIP runtime or launch error                            */
+  SGL_E_UNSUPPORTED = -5  /* e.g. an FFT length with a prime factor above 5         */
+} sgl_status;
+
+typedef enum { SGL_F64 = 0, SGL_F32 = 1 } sgl_precision;
+
+/* Replace the NFFT by the exact NDFT of Def. 2.4 (the variant the paper uses
+ * to separate the NFFT error from the rest, Section 8, fourth test).  O(B^3)
+ * work per point: for testing only. */
+#define SGL_FLAG_EXACT_NDFT (1u << 0)
+
+typedef struct {
+  int32_t B;          /* bandwidth, 2 <= B <= 256 (Section 6 assumes B >= 2)              */
+  int32_t sigma;      /* integer oversampling factor, 2..4 (Section 2; Thm. 2.7 needs >= 2) */
+  int32_t q;          /* window cutoff, 1 <= q and 2q <= sigma*2B (q < sigma n, Section 2)  */
+  double rho;         /* <= 0: rho = max_i |x_i| (eq. nfsglft_rho); else >= max_i |x_i|     */
+  int32_t precision;  /* sgl_precision                                                      */
+  uint32_t flags;     /* SGL_FLAG_*                                                         */
+} sgl_params;
+
+/* Number of coefficients B(B+1)(2B+1)/6 (Section 1); -1 if B < 1. */
+int64_t sgl_num_coeffs(int32_t B);
+
+/* mu(n,l,m) = n(n-1)(2n-1)/6 + l(l+1) + m for |m| <= l < n (Section 1); -1 otherwise. */
+int64_t sgl_coeff_index(int32_t n, int32_t l, int32_t m);
+
+/* Reduced trigonometric grid of Remark 8.1: dims[0..2] = {4B, 2B, 2B}.
+ * eta buffers used by the stage entry points are dims[0]*dims[1]*dims[2]
+ * complex values, index ((k0 + 2B) * 2B + (k1 + B)) * 2B + (k2 + B) for
+ * k0 in [-2B, 2B), k1, k2 in [-B, B) -- the index sets I_{4B} x I_{2B} x I_{2B}. */
+sgl_status sgl_eta_dims(int32_t B, int32_t dims[3]);
+
+/* Create a plan for M points (Section 6 setup): validates the parameters,
+ * computes the transformed points x~_i = (arccos gamma(r_i), theta_i, phi_i)
+ * (eq. x_tilde) with rho of eq. nfsglft_rho, bins them into grid tiles,
+ * builds the conversion tables (in long double on the host) and the
+ * deconvolution factors, and allocates the workspace.
+ *   out        : receives the plan handle (host pointer)
+ *   p          : parameters (host pointer)
+ *   M          : number of points, 1 <= M < 2^31
+ *   points_dev : device pointer, M x 3 (double or float by p->precision);
+ *                may be freed once sgl_plan returns
+ *   hip_stream : hipStream_t used by every later call; NULL = null stream
+ * Synchronous.  Errors: SGL_E_INVAL (null pointers, bad parameters, NaN/Inf
+ * points), SGL_E_RANGE (p->rho > 0 but below max |x_i|), SGL_E_UNSUPPORTED,
+ * SGL_E_NOMEM, SGL_E_DEVICE.  On error *out is set to NULL. */
+sgl_status sgl_plan(sgl_plan_t *out, const sgl_params *p, int64_t M, const void *points_dev,
+                    void *hip_stream);
+
+/* f = Lambda fhat, approximately (Thm. 6.2 with the NFFT; exactly up to
+ * rounding with SGL_FLAG_EXACT_NDFT).
+ *   fhat_dev : Nc complex, coefficient order mu (input, not modified)
+ *   f_dev    : M complex, caller's point order (output, overwritten) */
+sgl_status sgl_forward(sgl_plan_t plan, const void *fhat_dev, void *f_dev);
+
+/* fhat = Lambda^H f (Cor. 6.3): exact adjoint of the fast forward.
+ *   f_dev    : M complex, caller's point order (input, not modified)
+ *   fhat_dev : Nc complex, order mu (output, overwritten) */
+sgl_status sgl_adjoint(sgl_plan_t plan, const void *f_dev, void *fhat_dev);
+
+/* Stage: the conversion alone (all factors of Thm. 6.2 right of N):
+ * fhat (Nc complex) -> eta on the reduced grid (see sgl_eta_dims). */
+sgl_status sgl_conv_forward(sgl_plan_t plan, const void *fhat_dev, void *eta_dev);
+
+/* Stage: adjoint of sgl_conv_forward (Cor. 6.3 without N^H). */
+sgl_status sgl_conv_adjoint(sgl_plan_t plan, const void *eta_dev, void *fhat_dev);
+
+/* Stage: the 3D NFFT of Section 2 (or the NDFT with SGL_FLAG_EXACT_NDFT)
+ * alone, evaluating p(x~_i) = sum_k eta_k e^{i <k, x~_i>} at the plan's
+ * transformed points: eta (reduced grid) -> f (M complex, caller's order). */
+sgl_status sgl_nfft_forward(sgl_plan_t plan, const void *eta_dev, void *f_dev);
+
+/* Stage: adjoint of sgl_nfft_forward: f (M complex) -> eta (reduced grid). */
+sgl_status sgl_nfft_adjoint(sgl_plan_t plan, const void *f_dev, void *eta_dev);
+
+/* The rho the plan uses (host pointer out). */
+sgl_status sgl_plan_rho(sgl_plan_t plan, double *rho);
+
+/* Informational: number of points, FFT grid sigma*n, stored (pruned) grid
+ * extents, gather tile edges, and bytes of device workspace.  info must
+ * hold 12 int64 values: {M, N0, N1, N2, E0, E1, E2, L0, L1, L2, bytes,
+ * gather_mode (0 = LDS tiles, 1 = direct)}. */
+sgl_status sgl_plan_info(sgl_plan_t plan, int64_t info[12]);
+
+/* Stages timed by the optional per-stage profiler (forward: radial and polar
+ * conversion, FFT passes A (along m), B (along k1), C (along k0), gather;
+ * adjoint: scatter, FFT passes C, B, A, polar and radial adjoint conversion;
+ * exact mode: NDFT and its adjoint). */
+enum {
+  SGL_STAGE_CONV_RADIAL = 0,
+  SGL_STAGE_CONV_POLAR,
+  SGL_STAGE_FFT_A,
+  SGL_STAGE_FFT_B,
+  SGL_STAGE_FFT_C,
+  SGL_STAGE_GATHER,
+  SGL_STAGE_SCATTER,
+  SGL_STAGE_FFT_CH,
+  SGL_STAGE_FFT_BH,
+  SGL_STAGE_FFT_AH,
+  SGL_STAGE_CONV_POLAR_ADJ,
+  SGL_STAGE_CONV_RADIAL_ADJ,
+  SGL_STAGE_NDFT,
+  SGL_STAGE_NDFT_ADJ,
+  SGL_NUM_STAGES
+};
+
+/* Enable (1) or disable (0) per-stage timing: while enabled, every kernel
+ * launch of the plan is bracketed by HIP events recorded on the plan's
+ * stream.  Enabling allocates the events (SGL_E_NOMEM / SGL_E_DEVICE). */
+sgl_status sgl_plan_profile(sgl_plan_t plan, int32_t enable);
+
+/* Wait for the plan's stream and return, per stage, the summed event time in
+ * milliseconds and the number of launches since the last reset (host arrays
+ * of SGL_NUM_STAGES entries).  reset != 0 zeroes the totals afterwards. */
+sgl_status sgl_plan_stage_times(sgl_plan_t plan, double ms[SGL_NUM_STAGES], int64_t counts[SGL_NUM_STAGES],
+                                int32_t reset);
+
+/* Release the plan and its device memory (waits for its stream). */
+sgl_status sgl_destroy(sgl_plan_t plan);
+
+/* Static description of a status code. */
+const char *sgl_status_string(sgl_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SGL_H */

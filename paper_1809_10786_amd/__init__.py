@@ -1,0 +1,221 @@
+"""Fast SGL Fourier transform for scattered data (NFSGLFT) on MI355X.
+
+Thin ctypes binding over the C-ABI library ``libsgl.so`` (include/sgl.h).
+Argument marshalling only: every step of the transform runs in the library's
+HIP kernels.  PyTorch provides device memory and the current stream.  There
+is no fallback -- if the library is missing, importing the binding raises.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsgl.so")
+
+SGL_OK, SGL_E_INVAL, SGL_E_RANGE, SGL_E_NOMEM, SGL_E_DEVICE, SGL_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
+SGL_F64, SGL_F32 = 0, 1
+SGL_FLAG_EXACT_NDFT = 1
+
+# Every symbol include/sgl.h declares.
+SYMBOLS = (
+    "sgl_num_coeffs", "sgl_coeff_index", "sgl_eta_dims", "sgl_plan", "sgl_forward", "sgl_adjoint",
+    "sgl_conv_forward", "sgl_conv_adjoint", "sgl_nfft_forward", "sgl_nfft_adjoint", "sgl_plan_rho",
+    "sgl_plan_info", "sgl_plan_profile", "sgl_plan_stage_times", "sgl_destroy", "sgl_status_string",
+)
+
+STAGES = ("conv_radial", "conv_polar", "fft_A", "fft_B", "fft_C", "gather", "scatter", "fft_Ch", "fft_Bh",
+          "fft_Ah", "conv_polar_adj", "conv_radial_adj", "ndft", "ndft_adj")
+
+
+class SglParams(ctypes.Structure):
+    _fields_ = [("B", ctypes.c_int32), ("sigma", ctypes.c_int32), ("q", ctypes.c_int32),
+                ("rho", ctypes.c_double), ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class SglError(RuntimeError):
+    def __init__(self, status, what):
+        self.status = status
+        super().__init__(f"{what}: {status_string(status)} ({status})")
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run paper_1809_10786_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        L.sgl_num_coeffs.argtypes, L.sgl_num_coeffs.restype = [i32], i64
+        L.sgl_coeff_index.argtypes, L.sgl_coeff_index.restype = [i32, i32, i32], i64
+        L.sgl_eta_dims.argtypes, L.sgl_eta_dims.restype = [i32, ctypes.POINTER(i32)], ctypes.c_int
+        L.sgl_plan.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(SglParams), i64, vp, vp]
+        L.sgl_plan.restype = ctypes.c_int
+        for name in ("sgl_forward", "sgl_adjoint", "sgl_conv_forward", "sgl_conv_adjoint",
+                     "sgl_nfft_forward", "sgl_nfft_adjoint"):
+            fn = getattr(L, name)
+            fn.argtypes, fn.restype = [vp, vp, vp], ctypes.c_int
+        L.sgl_plan_rho.argtypes, L.sgl_plan_rho.restype = [vp, ctypes.POINTER(ctypes.c_double)], ctypes.c_int
+        L.sgl_plan_info.argtypes, L.sgl_plan_info.restype = [vp, ctypes.POINTER(i64)], ctypes.c_int
+        L.sgl_plan_profile.argtypes, L.sgl_plan_profile.restype = [vp, i32], ctypes.c_int
+        L.sgl_plan_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), i32]
+        L.sgl_plan_stage_times.restype = ctypes.c_int
+        L.sgl_destroy.argtypes, L.sgl_destroy.restype = [vp], ctypes.c_int
+        L.sgl_status_string.argtypes, L.sgl_status_string.restype = [ctypes.c_int], ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def status_string(s):
+    return lib().sgl_status_string(s).decode()
+
+
+def _check(st, what):
+    if st != SGL_OK:
+        raise SglError(st, what)
+
+
+def num_coeffs(B):
+    return int(lib().sgl_num_coeffs(B))
+
+
+def coeff_index(n, l, m):
+    return int(lib().sgl_coeff_index(n, l, m))
+
+
+def eta_dims(B):
+    d = (ctypes.c_int32 * 3)()
+    _check(lib().sgl_eta_dims(B, d), "sgl_eta_dims")
+    return tuple(d)
+
+
+class Plan:
+    """NFSGLFT plan for fixed points on the current CUDA (HIP) device.
+
+    points    : torch tensor (M, 3), float64 for precision "f64", float32 for "f32", on the GPU
+    B         : bandwidth; sigma, q: NFFT oversampling and cutoff; rho <= 0 picks max |x_i|
+    exact_ndft: evaluate the trigonometric polynomial exactly (test mode)
+    """
+
+    def __init__(self, points, B, sigma=2, q=6, rho=0.0, precision="f64", exact_ndft=False, stream=None):
+        import torch
+
+        self._torch = torch
+        if precision not in ("f64", "f32"):
+            raise ValueError("precision must be 'f64' or 'f32'")
+        self.precision = precision
+        self.real_dtype = torch.float64 if precision == "f64" else torch.float32
+        self.complex_dtype = torch.complex128 if precision == "f64" else torch.complex64
+        if not points.is_cuda or points.dtype != self.real_dtype or points.dim() != 2 or points.shape[1] != 3:
+            raise ValueError(f"points must be a CUDA tensor (M, 3) of {self.real_dtype}")
+        points = points.contiguous()
+        self.B, self.M = int(B), int(points.shape[0])
+        self.device = points.device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        prm = SglParams(self.B, int(sigma), int(q), float(rho), SGL_F64 if precision == "f64" else SGL_F32,
+                        SGL_FLAG_EXACT_NDFT if exact_ndft else 0)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            st = lib().sgl_plan(ctypes.byref(h), ctypes.byref(prm), self.M, ctypes.c_void_p(points.data_ptr()),
+                                ctypes.c_void_p(self.stream.cuda_stream))
+        _check(st, "sgl_plan")
+        self._h = h
+        self.nc = num_coeffs(self.B)
+        self.eta_shape = eta_dims(self.B)
+
+    # -- properties --------------------------------------------------------
+    @property
+    def rho(self):
+        r = ctypes.c_double()
+        _check(lib().sgl_plan_rho(self._h, ctypes.byref(r)), "sgl_plan_rho")
+        return r.value
+
+    def info(self):
+        v = (ctypes.c_int64 * 12)()
+        _check(lib().sgl_plan_info(self._h, v), "sgl_plan_info")
+        keys = ("M", "N0", "N1", "N2", "E0", "E1", "E2", "L0", "L1", "L2", "bytes", "gather_mode")
+        return dict(zip(keys, list(v)))
+
+    def profile(self, enable=True):
+        """Per-stage HIP-event timing of every launch on the plan's stream."""
+        _check(lib().sgl_plan_profile(self._h, 1 if enable else 0), "sgl_plan_profile")
+
+    def stage_times(self, reset=True):
+        """{stage: (total ms, launches)} since the last reset (waits for the stream)."""
+        n = len(STAGES)
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int64 * n)()
+        _check(lib().sgl_plan_stage_times(self._h, ms, cnt, 1 if reset else 0), "sgl_plan_stage_times")
+        return {STAGES[i]: (ms[i], cnt[i]) for i in range(n) if cnt[i]}
+
+    # -- helpers -------------------------------------------------------------
+    def _in(self, x, n, what):
+        if not x.is_cuda or x.dtype != self.complex_dtype or x.numel() != n:
+            raise ValueError(f"{what} must be a CUDA {self.complex_dtype} tensor with {n} elements")
+        return x.contiguous()
+
+    def _out(self, n, out):
+        if out is None:
+            return self._torch.empty(n, dtype=self.complex_dtype, device=self.device)
+        if out.dtype != self.complex_dtype or out.numel() != n or not out.is_contiguous():
+            raise ValueError("bad output tensor")
+        return out
+
+    def _call(self, name, x, y):
+        fn = getattr(lib(), name)
+        _check(fn(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr())), name)
+
+    # -- transforms ----------------------------------------------------------
+    def forward(self, fhat, out=None):
+        """f = Lambda fhat (M values, caller's point order)."""
+        x = self._in(fhat, self.nc, "fhat")
+        y = self._out(self.M, out)
+        self._call("sgl_forward", x, y)
+        return y
+
+    def adjoint(self, f, out=None):
+        """fhat = Lambda^H f (Nc values, coefficient order mu)."""
+        x = self._in(f, self.M, "f")
+        y = self._out(self.nc, out)
+        self._call("sgl_adjoint", x, y)
+        return y
+
+    def conv_forward(self, fhat, out=None):
+        x = self._in(fhat, self.nc, "fhat")
+        n = self.eta_shape[0] * self.eta_shape[1] * self.eta_shape[2]
+        y = self._out(n, out)
+        self._call("sgl_conv_forward", x, y)
+        return y.view(self.eta_shape)
+
+    def conv_adjoint(self, eta, out=None):
+        n = self.eta_shape[0] * self.eta_shape[1] * self.eta_shape[2]
+        x = self._in(eta.reshape(-1), n, "eta")
+        y = self._out(self.nc, out)
+        self._call("sgl_conv_adjoint", x, y)
+        return y
+
+    def nfft_forward(self, eta, out=None):
+        n = self.eta_shape[0] * self.eta_shape[1] * self.eta_shape[2]
+        x = self._in(eta.reshape(-1), n, "eta")
+        y = self._out(self.M, out)
+        self._call("sgl_nfft_forward", x, y)
+        return y
+
+    def nfft_adjoint(self, f, out=None):
+        n = self.eta_shape[0] * self.eta_shape[1] * self.eta_shape[2]
+        x = self._in(f, self.M, "f")
+        y = self._out(n, out)
+        self._call("sgl_nfft_adjoint", x, y)
+        return y.view(self.eta_shape)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().sgl_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

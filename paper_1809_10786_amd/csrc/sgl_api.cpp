@@ -1,0 +1,548 @@
+// C-ABI entry points (include/sgl.h): argument checks, plan construction
+// (points, bins, tables, workspace), and the composition of the forward and
+// adjoint transforms out of the stage kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "sgl_internal.h"
+
+using namespace sgl;
+
+struct sgl_plan_s {
+  Plan p;
+};
+
+namespace {
+
+constexpr double kPi = 3.141592653589793238462643383279502884;
+constexpr size_t kLdsBudget = 64 * 1024;
+
+sgl_status from_hip(hipError_t e) {
+  if (e == hipSuccess) return SGL_OK;
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return SGL_E_NOMEM;
+  return SGL_E_DEVICE;
+}
+
+#define SGL_TRY(expr)                       \
+  do {                                      \
+    const hipError_t e_ = (expr);           \
+    if (e_ != hipSuccess) return from_hip(e_); \
+  } while (0)
+
+bool radices_of(int L, FftPass &fp) {
+  fp.L = L;
+  fp.nstages = 0;
+  int r = L;
+  for (int f : {8, 4, 2, 3, 5})
+    while (r % f == 0) {
+      if (fp.nstages == kMaxStages) return false;
+      fp.radix[fp.nstages++] = f;
+      r /= f;
+    }
+  return r == 1;
+}
+
+int lines_per_group(int L, size_t elem) {
+  int W = 1;
+  while (W < 32 && 2 * (size_t)L * (W * 2) * elem <= kLdsBudget) W *= 2;
+  return W;
+}
+
+void free_plan(Plan &p) {
+  void *bufs[] = {p.pts, p.perm, p.tile_start, p.chunks, p.krad, p.kpol, p.deconv, p.twiddle,
+                  p.beta, p.eta, p.bufX, p.bufY, p.ptsxyz};
+  for (void *b : bufs)
+    if (b) hipFree(b);
+}
+
+template <class T>
+hipError_t dev_alloc(Plan &p, T **ptr, size_t bytes) {
+  void *v = nullptr;
+  const hipError_t e = hipMalloc(&v, bytes ? bytes : 16);
+  if (e == hipSuccess) {
+    *ptr = (T *)v;
+    p.bytes += bytes;
+  }
+  return e;
+}
+
+template <class R>
+hipError_t upload_real(Plan &p, void **dst, const std::vector<long double> &v) {
+  std::vector<R> h(v.size());
+  for (size_t i = 0; i < v.size(); ++i) h[i] = (R)v[i];
+  hipError_t e = dev_alloc(p, dst, h.size() * sizeof(R));
+  if (e != hipSuccess) return e;
+  return hipMemcpy(*dst, h.data(), h.size() * sizeof(R), hipMemcpyHostToDevice);
+}
+
+template <class R>
+hipError_t upload_twiddles(Plan &p) {
+  std::vector<R> h;
+  for (int j = 0; j < 3; ++j) {
+    std::vector<long double> re, im;
+    build_twiddles(p.N[j], +1, re, im);
+    p.tw_off[j] = (int64_t)h.size() / 2;
+    for (int t = 0; t < p.N[j]; ++t) {
+      h.push_back((R)re[t]);
+      h.push_back((R)im[t]);
+    }
+  }
+  hipError_t e = dev_alloc(p, &p.twiddle, h.size() * sizeof(R));
+  if (e != hipSuccess) return e;
+  return hipMemcpy(p.twiddle, h.data(), h.size() * sizeof(R), hipMemcpyHostToDevice);
+}
+
+bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
+  const char *x = (const char *)a, *y = (const char *)b;
+  return x < y + nb && y < x + na;
+}
+
+size_t cbytes(const Plan &p) { return p.prec == SGL_F64 ? 16 : 8; }
+
+// Geometry of grids, bins and blocks (host only).
+sgl_status setup_geometry(Plan &p) {
+  const int B = p.B;
+  p.n[0] = 4 * B;
+  p.n[1] = 2 * B;
+  p.n[2] = 2 * B;
+  for (int j = 0; j < 3; ++j) p.N[j] = p.sigma * p.n[j];
+  if (p.N[0] > 2048 || p.N[1] > 1024 || p.N[2] > 1024) return SGL_E_UNSUPPORTED;
+  FftPass tmp;
+  for (int j = 0; j < 3; ++j)
+    if (!radices_of(p.N[j], tmp)) return SGL_E_UNSUPPORTED;
+  p.lambda = p.sigma * (double)p.q / ((2.0 * p.sigma - 1.0) * kPi);
+  for (int j = 0; j < 3; ++j) {
+    if (j < 2 && p.N[j] / 2 + 2 * p.q < p.N[j]) {
+      p.pruned[j] = true;
+      p.E[j] = p.N[j] / 2 + 2 * p.q;
+      p.lo[j] = 1 - p.q;
+    } else {
+      p.pruned[j] = false;
+      p.E[j] = p.N[j];
+      p.lo[j] = 0;
+    }
+    p.NB[j] = (j < 2) ? p.N[j] / 2 + 1 : p.N[j];
+  }
+  // gather tiles: the largest edges (<= 8) whose window box fits in LDS
+  const size_t cb = cbytes(p);
+  int L[3] = {8, 8, 8};
+  auto box = [&](const int *l) { return (size_t)(l[0] + 2 * p.q - 1) * (l[1] + 2 * p.q - 1) * (l[2] + 2 * p.q - 1) * cb; };
+  while (box(L) > kLdsBudget && (L[0] > 4 || L[1] > 4 || L[2] > 4)) {
+    int j = (L[0] >= L[1] && L[0] >= L[2]) ? 0 : (L[1] >= L[2] ? 1 : 2);
+    L[j] /= 2;
+  }
+  p.gather_mode = box(L) <= kLdsBudget ? 0 : 1;
+  p.ntiles = 1;
+  for (int j = 0; j < 3; ++j) {
+    p.L[j] = std::min(L[j], p.NB[j]);
+    p.T[j] = (p.NB[j] + p.L[j] - 1) / p.L[j];
+    p.X[j] = p.L[j] + 2 * p.q - 1;
+    p.ntiles *= p.T[j];
+  }
+  if ((uint64_t)p.ntiles * p.L[0] * p.L[1] * p.L[2] >= (1ull << 32)) return SGL_E_UNSUPPORTED;
+  // scatter blocks over stored cells
+  // 16^3 cells (FP32) or 16 x 16 x 8 (FP64): 32 KB of LDS accumulators
+  const int lo_edge[3] = {16, 16, p.prec == SGL_F64 ? 8 : 16};
+  p.nblocks = 1;
+  for (int j = 0; j < 3; ++j) {
+    p.Lo[j] = std::min(lo_edge[j], p.E[j]);
+    p.To[j] = (p.E[j] + p.Lo[j] - 1) / p.Lo[j];
+    p.nblocks *= p.To[j];
+  }
+  // worst-case number of bin rows a block visits must fit the kernel's table
+  int64_t rows = 3;
+  for (int j = 0; j < 2; ++j) {
+    const int span = p.Lo[j] + 2 * p.q - 1;
+    rows *= std::min<int64_t>(p.T[j], span / p.L[j] + 2 + (p.pruned[j] ? 0 : 2));
+  }
+  if (rows > 512) return SGL_E_UNSUPPORTED;
+  // FFT passes: [outer][axis][inner] views
+  auto pass = [&](FftPass &fp, int j, int outer, int inner, int nin, int in_off, int nout, int out_off, int sign) {
+    radices_of(p.N[j], fp);
+    fp.outer = outer;
+    fp.inner = inner;
+    fp.nin = nin;
+    fp.in_off = in_off;
+    fp.nout = nout;
+    fp.out_off = out_off;
+    fp.sign = sign;
+    fp.W = lines_per_group(p.N[j], cb);
+  };
+  const int n0 = p.n[0], n1 = p.n[1], n2 = p.n[2];
+  pass(p.passA, 2, n0 * n1, 1, n2, -n2 / 2, p.N[2], 0, +1);
+  pass(p.passB, 1, n0, p.N[2], n1, -n1 / 2, p.E[1], p.lo[1], +1);
+  pass(p.passC, 0, 1, p.E[1] * p.N[2], n0, -n0 / 2, p.E[0], p.lo[0], +1);
+  pass(p.passCh, 0, 1, p.E[1] * p.N[2], p.E[0], p.lo[0], n0, -n0 / 2, -1);
+  pass(p.passBh, 1, n0, p.N[2], p.E[1], p.lo[1], n1, -n1 / 2, -1);
+  pass(p.passAh, 2, n0 * n1, 1, p.N[2], 0, n2, -n2 / 2, -1);
+  return SGL_OK;
+}
+
+template <class R>
+sgl_status build_tables(Plan &p) {
+  std::vector<long double> kr, kp, dc;
+  build_radial_table(p.B, p.rho, kr, p.krad_off);
+  build_polar_table(p.B, kp, p.kpol_off);
+  build_deconv(p, dc);
+  SGL_TRY(upload_real<R>(p, &p.krad, kr));
+  SGL_TRY(upload_real<R>(p, &p.kpol, kp));
+  SGL_TRY(upload_real<R>(p, &p.deconv, dc));
+  SGL_TRY(upload_twiddles<R>(p));
+  return SGL_OK;
+}
+
+sgl_status make_plan(Plan &p, const void *points) {
+  // 1. radius reduction: rho and finiteness (eq. nfsglft_rho)
+  const int nrb = (int)std::min<int64_t>(1024, (p.M + 255) / 256);
+  double *partial = nullptr;
+  SGL_TRY(hipMalloc(&partial, 2 * nrb * sizeof(double)));
+  hipError_t e = launch_point_radius(p, points, partial, nrb);
+  std::vector<double> hp(2 * nrb);
+  if (e == hipSuccess) e = hipMemcpyAsync(hp.data(), partial, hp.size() * sizeof(double), hipMemcpyDeviceToHost, p.stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(p.stream);
+  hipFree(partial);
+  SGL_TRY(e);
+  double maxr = 0.0, bad = 0.0;
+  for (int b = 0; b < nrb; ++b) {
+    maxr = std::max(maxr, hp[2 * b]);
+    bad += hp[2 * b + 1];
+  }
+  if (bad > 0) return SGL_E_INVAL;
+  if (p.rho > 0.0) {
+    if (p.rho < maxr) return SGL_E_RANGE;
+  } else {
+    p.rho = maxr > 0.0 ? maxr : 1.0;
+  }
+  // 2. geometry
+  sgl_status st = setup_geometry(p);
+  if (st != SGL_OK) return st;
+  // 3. points: transform, key, sort into tiles
+  const size_t M = (size_t)p.M;
+  const size_t rec = p.prec == SGL_F64 ? sizeof(PointRec<double>) : sizeof(PointRec<float>);
+  SGL_TRY(dev_alloc(p, &p.pts, M * rec));
+  SGL_TRY(dev_alloc(p, &p.perm, M * sizeof(int32_t)));
+  SGL_TRY(dev_alloc(p, &p.tile_start, (p.ntiles + 1) * sizeof(int32_t)));
+  if (p.flags & SGL_FLAG_EXACT_NDFT) SGL_TRY(dev_alloc(p, &p.ptsxyz, 3 * M * sizeof(double)));
+  uint32_t *keys = nullptr;
+  int32_t *idx = nullptr;
+  void *unsorted = nullptr;
+  e = hipMalloc(&keys, 2 * M * sizeof(uint32_t));
+  if (e == hipSuccess) e = hipMalloc(&idx, M * sizeof(int32_t));
+  if (e == hipSuccess) e = hipMalloc(&unsorted, M * rec);
+  if (e == hipSuccess) e = launch_point_prep(p, points, keys, idx, unsorted);
+  if (e == hipSuccess) e = launch_point_sort(p, keys, idx, unsorted);
+  if (keys) hipFree(keys);
+  if (idx) hipFree(idx);
+  if (unsorted) hipFree(unsorted);
+  SGL_TRY(e);
+  // 4. gather work list: chunks of at most kChunk points of one tile
+  std::vector<int32_t> ts(p.ntiles + 1);
+  SGL_TRY(hipMemcpy(ts.data(), p.tile_start, ts.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+  const int kChunk = 512;
+  std::vector<int32_t> ch;
+  for (int64_t t = 0; t < p.ntiles; ++t)
+    for (int s = ts[t]; s < ts[t + 1]; s += kChunk) {
+      ch.push_back((int32_t)t);
+      ch.push_back(s);
+      ch.push_back(std::min(kChunk, ts[t + 1] - s));
+    }
+  p.nchunks = (int64_t)ch.size() / 3;
+  SGL_TRY(dev_alloc(p, &p.chunks, ch.size() * sizeof(int32_t)));
+  if (!ch.empty()) SGL_TRY(hipMemcpy(p.chunks, ch.data(), ch.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  // 5. tables
+  st = p.prec == SGL_F64 ? build_tables<double>(p) : build_tables<float>(p);
+  if (st != SGL_OK) return st;
+  // 6. workspace
+  const size_t cb = cbytes(p);
+  const int B = p.B;
+  const size_t nbeta = (size_t)(2 * B - 1) * B * B;  // sum_m (B - |m|) (2B - 1) = B^2 (2B - 1)
+  const size_t neta = (size_t)p.n[0] * p.n[1] * p.n[2];
+  const size_t nT1 = (size_t)p.n[0] * p.n[1] * p.N[2];
+  const size_t nT2 = (size_t)p.n[0] * p.E[1] * p.N[2];
+  const size_t nG = (size_t)p.E[0] * p.E[1] * p.E[2];
+  SGL_TRY(dev_alloc(p, &p.beta, nbeta * cb));
+  SGL_TRY(dev_alloc(p, &p.eta, neta * cb));
+  SGL_TRY(dev_alloc(p, &p.bufX, std::max(nT1, nG) * cb));
+  SGL_TRY(dev_alloc(p, &p.bufY, nT2 * cb));
+  SGL_TRY(hipStreamSynchronize(p.stream));
+  return SGL_OK;
+}
+
+sgl_status check_plan(sgl_plan_t plan) { return plan ? SGL_OK : SGL_E_INVAL; }
+
+// ---- per-stage event timing ----
+void prof_collect(Plan &p) {
+  Profiler &pr = p.prof;
+  for (size_t i = 0; i < pr.stage.size(); ++i) {
+    float ms = 0.0f;
+    if (hipEventSynchronize(pr.pool[2 * i + 1]) == hipSuccess &&
+        hipEventElapsedTime(&ms, pr.pool[2 * i], pr.pool[2 * i + 1]) == hipSuccess) {
+      pr.ms[pr.stage[i]] += ms;
+      pr.count[pr.stage[i]] += 1;
+    }
+  }
+  pr.stage.clear();
+  pr.next = 0;
+}
+
+struct Stage {
+  Plan &p;
+  bool on;
+  Stage(Plan &p_, int stage) : p(p_), on(p_.prof.on) {
+    if (!on) return;
+    if (p.prof.next + 2 > p.prof.pool.size()) prof_collect(p);
+    hipEventRecord(p.prof.pool[p.prof.next++], p.stream);
+    p.prof.stage.push_back(stage);
+  }
+  ~Stage() {
+    if (on) hipEventRecord(p.prof.pool[p.prof.next++], p.stream);
+  }
+};
+
+#define SGL_STAGE(id, expr)      \
+  do {                           \
+    Stage st_(p, id);            \
+    SGL_TRY(expr);               \
+  } while (0)
+
+sgl_status conv_fwd(Plan &p, const void *fhat, void *eta) {
+  SGL_STAGE(SGL_STAGE_CONV_RADIAL, launch_conv_radial(p, fhat));
+  SGL_STAGE(SGL_STAGE_CONV_POLAR, launch_conv_polar(p, eta));
+  return SGL_OK;
+}
+
+sgl_status conv_adj(Plan &p, const void *eta, void *fhat) {
+  SGL_STAGE(SGL_STAGE_CONV_POLAR_ADJ, launch_conv_polar_adj(p, eta));
+  SGL_STAGE(SGL_STAGE_CONV_RADIAL_ADJ, launch_conv_radial_adj(p, fhat));
+  return SGL_OK;
+}
+
+sgl_status nfft_fwd(Plan &p, const void *eta, void *f) {
+  if (p.flags & SGL_FLAG_EXACT_NDFT) {
+    SGL_STAGE(SGL_STAGE_NDFT, launch_ndft_forward(p, eta, f));
+    return SGL_OK;
+  }
+  SGL_STAGE(SGL_STAGE_FFT_A, launch_fft_pass(p, p.passA, eta, p.bufX, 2, 1, 0));
+  SGL_STAGE(SGL_STAGE_FFT_B, launch_fft_pass(p, p.passB, p.bufX, p.bufY, 1, 0, 0));
+  SGL_STAGE(SGL_STAGE_FFT_C, launch_fft_pass(p, p.passC, p.bufY, p.bufX, 0, 0, 0));
+  SGL_STAGE(SGL_STAGE_GATHER, launch_gather(p, p.bufX, f));
+  return SGL_OK;
+}
+
+sgl_status nfft_adj(Plan &p, const void *f, void *eta) {
+  if (p.flags & SGL_FLAG_EXACT_NDFT) {
+    SGL_STAGE(SGL_STAGE_NDFT_ADJ, launch_ndft_adjoint(p, f, eta));
+    return SGL_OK;
+  }
+  SGL_STAGE(SGL_STAGE_SCATTER, launch_scatter(p, f, p.bufX));
+  SGL_STAGE(SGL_STAGE_FFT_CH, launch_fft_pass(p, p.passCh, p.bufX, p.bufY, 0, 0, 0));
+  SGL_STAGE(SGL_STAGE_FFT_BH, launch_fft_pass(p, p.passBh, p.bufY, p.bufX, 1, 0, 0));
+  SGL_STAGE(SGL_STAGE_FFT_AH, launch_fft_pass(p, p.passAh, p.bufX, eta, 2, 2, 0));
+  return SGL_OK;
+}
+
+void prof_release(Plan &p) {
+  if (!p.prof.pool.empty()) {
+    hipStreamSynchronize(p.stream);
+    for (hipEvent_t e : p.prof.pool) hipEventDestroy(e);
+  }
+  p.prof.pool.clear();
+  p.prof.stage.clear();
+  p.prof.next = 0;
+  p.prof.on = false;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t sgl_num_coeffs(int32_t B) {
+  if (B < 1) return -1;
+  return (int64_t)B * (B + 1) * (2 * B + 1) / 6;
+}
+
+int64_t sgl_coeff_index(int32_t n, int32_t l, int32_t m) {
+  if (n < 1 || l < 0 || l >= n || m < -l || m > l) return -1;
+  return (int64_t)n * (n - 1) * (2 * n - 1) / 6 + (int64_t)l * (l + 1) + m;
+}
+
+sgl_status sgl_eta_dims(int32_t B, int32_t dims[3]) {
+  if (!dims || B < 2 || B > 256) return SGL_E_INVAL;
+  dims[0] = 4 * B;
+  dims[1] = 2 * B;
+  dims[2] = 2 * B;
+  return SGL_OK;
+}
+
+sgl_status sgl_plan(sgl_plan_t *out, const sgl_params *prm, int64_t M, const void *points_dev, void *hip_stream) {
+  if (!out) return SGL_E_INVAL;
+  *out = nullptr;
+  if (!prm || !points_dev) return SGL_E_INVAL;
+  if (prm->B < 2 || prm->B > 256) return SGL_E_INVAL;
+  if (prm->sigma < 2 || prm->sigma > 4) return SGL_E_INVAL;
+  if (prm->q < 1 || prm->q > 16 || 2 * prm->q > prm->sigma * 2 * prm->B) return SGL_E_INVAL;
+  if (prm->precision != SGL_F64 && prm->precision != SGL_F32) return SGL_E_INVAL;
+  if (prm->flags & ~(uint32_t)SGL_FLAG_EXACT_NDFT) return SGL_E_INVAL;
+  if (!std::isfinite(prm->rho)) return SGL_E_INVAL;
+  if (M < 1 || M > 0x7fffffffLL) return SGL_E_INVAL;
+  sgl_plan_s *h = new (std::nothrow) sgl_plan_s;
+  if (!h) return SGL_E_NOMEM;
+  Plan &p = h->p;
+  p.B = prm->B;
+  p.sigma = prm->sigma;
+  p.q = prm->q;
+  p.prec = prm->precision;
+  p.flags = prm->flags;
+  p.M = M;
+  p.rho = prm->rho > 0 ? prm->rho : 0.0;
+  p.stream = (hipStream_t)hip_stream;
+  if (hipGetDevice(&p.device) != hipSuccess) {
+    delete h;
+    return SGL_E_DEVICE;
+  }
+  const sgl_status st = make_plan(p, points_dev);
+  if (st != SGL_OK) {
+    hipStreamSynchronize(p.stream);
+    free_plan(p);
+    delete h;
+    return st;
+  }
+  *out = h;
+  return SGL_OK;
+}
+
+sgl_status sgl_conv_forward(sgl_plan_t plan, const void *fhat_dev, void *eta_dev) {
+  if (check_plan(plan) != SGL_OK || !fhat_dev || !eta_dev) return SGL_E_INVAL;
+  Plan &p = plan->p;
+  const size_t cb = cbytes(p);
+  if (overlaps(fhat_dev, sgl_num_coeffs(p.B) * cb, eta_dev, (size_t)p.n[0] * p.n[1] * p.n[2] * cb)) return SGL_E_INVAL;
+  return conv_fwd(p, fhat_dev, eta_dev);
+}
+
+sgl_status sgl_conv_adjoint(sgl_plan_t plan, const void *eta_dev, void *fhat_dev) {
+  if (check_plan(plan) != SGL_OK || !fhat_dev || !eta_dev) return SGL_E_INVAL;
+  Plan &p = plan->p;
+  const size_t cb = cbytes(p);
+  if (overlaps(fhat_dev, sgl_num_coeffs(p.B) * cb, eta_dev, (size_t)p.n[0] * p.n[1] * p.n[2] * cb)) return SGL_E_INVAL;
+  return conv_adj(p, eta_dev, fhat_dev);
+}
+
+sgl_status sgl_nfft_forward(sgl_plan_t plan, const void *eta_dev, void *f_dev) {
+  if (check_plan(plan) != SGL_OK || !eta_dev || !f_dev) return SGL_E_INVAL;
+  Plan &p = plan->p;
+  const size_t cb = cbytes(p);
+  if (overlaps(eta_dev, (size_t)p.n[0] * p.n[1] * p.n[2] * cb, f_dev, (size_t)p.M * cb)) return SGL_E_INVAL;
+  return nfft_fwd(p, eta_dev, f_dev);
+}
+
+sgl_status sgl_nfft_adjoint(sgl_plan_t plan, const void *f_dev, void *eta_dev) {
+  if (check_plan(plan) != SGL_OK || !eta_dev || !f_dev) return SGL_E_INVAL;
+  Plan &p = plan->p;
+  const size_t cb = cbytes(p);
+  if (overlaps(eta_dev, (size_t)p.n[0] * p.n[1] * p.n[2] * cb, f_dev, (size_t)p.M * cb)) return SGL_E_INVAL;
+  return nfft_adj(p, f_dev, eta_dev);
+}
+
+sgl_status sgl_forward(sgl_plan_t plan, const void *fhat_dev, void *f_dev) {
+  if (check_plan(plan) != SGL_OK || !fhat_dev || !f_dev) return SGL_E_INVAL;
+  Plan &p = plan->p;
+  const size_t cb = cbytes(p);
+  if (overlaps(fhat_dev, sgl_num_coeffs(p.B) * cb, f_dev, (size_t)p.M * cb)) return SGL_E_INVAL;
+  const sgl_status st = conv_fwd(p, fhat_dev, p.eta);
+  if (st != SGL_OK) return st;
+  return nfft_fwd(p, p.eta, f_dev);
+}
+
+sgl_status sgl_adjoint(sgl_plan_t plan, const void *f_dev, void *fhat_dev) {
+  if (check_plan(plan) != SGL_OK || !fhat_dev || !f_dev) return SGL_E_INVAL;
+  Plan &p = plan->p;
+  const size_t cb = cbytes(p);
+  if (overlaps(fhat_dev, sgl_num_coeffs(p.B) * cb, f_dev, (size_t)p.M * cb)) return SGL_E_INVAL;
+  const sgl_status st = nfft_adj(p, f_dev, p.eta);
+  if (st != SGL_OK) return st;
+  return conv_adj(p, p.eta, fhat_dev);
+}
+
+sgl_status sgl_plan_rho(sgl_plan_t plan, double *rho) {
+  if (check_plan(plan) != SGL_OK || !rho) return SGL_E_INVAL;
+  *rho = plan->p.rho;
+  return SGL_OK;
+}
+
+sgl_status sgl_plan_info(sgl_plan_t plan, int64_t info[12]) {
+  if (check_plan(plan) != SGL_OK || !info) return SGL_E_INVAL;
+  const Plan &p = plan->p;
+  const int64_t v[12] = {p.M, p.N[0], p.N[1], p.N[2], p.E[0], p.E[1], p.E[2],
+                         p.L[0], p.L[1], p.L[2], (int64_t)p.bytes, p.gather_mode};
+  std::memcpy(info, v, sizeof(v));
+  return SGL_OK;
+}
+
+sgl_status sgl_plan_profile(sgl_plan_t plan, int32_t enable) {
+  if (check_plan(plan) != SGL_OK) return SGL_E_INVAL;
+  Plan &p = plan->p;
+  if (!enable) {
+    prof_collect(p);
+    p.prof.on = false;
+    return SGL_OK;
+  }
+  if (p.prof.pool.empty()) {
+    p.prof.pool.resize(8192);
+    for (auto &e : p.prof.pool) {
+      const hipError_t err = hipEventCreate(&e);
+      if (err != hipSuccess) {
+        e = nullptr;
+        for (auto &x : p.prof.pool)
+          if (x) hipEventDestroy(x);
+        p.prof.pool.clear();
+        return from_hip(err);
+      }
+    }
+  }
+  p.prof.on = true;
+  return SGL_OK;
+}
+
+sgl_status sgl_plan_stage_times(sgl_plan_t plan, double ms[SGL_NUM_STAGES], int64_t counts[SGL_NUM_STAGES],
+                                int32_t reset) {
+  if (check_plan(plan) != SGL_OK || !ms || !counts) return SGL_E_INVAL;
+  Plan &p = plan->p;
+  prof_collect(p);
+  for (int i = 0; i < SGL_NUM_STAGES; ++i) {
+    ms[i] = p.prof.ms[i];
+    counts[i] = p.prof.count[i];
+    if (reset) {
+      p.prof.ms[i] = 0.0;
+      p.prof.count[i] = 0;
+    }
+  }
+  return SGL_OK;
+}
+
+sgl_status sgl_destroy(sgl_plan_t plan) {
+  if (!plan) return SGL_E_INVAL;
+  prof_release(plan->p);
+  hipStreamSynchronize(plan->p.stream);
+  free_plan(plan->p);
+  delete plan;
+  return SGL_OK;
+}
+
+const char *sgl_status_string(sgl_status s) {
+  switch (s) {
+    case SGL_OK: return "ok";
+    case SGL_E_INVAL: return "invalid argument";
+    case SGL_E_RANGE: return "rho smaller than the largest point radius";
+    case SGL_E_NOMEM: return "out of memory";
+    case SGL_E_DEVICE: return "HIP device or launch error";
+    case SGL_E_UNSUPPORTED: return "unsupported configuration";
+  }
+  return "unknown status";
+}
+
+}  // extern "C"

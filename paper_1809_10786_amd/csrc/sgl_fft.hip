@@ -1,0 +1,234 @@
+// One pass of the 3D FFT of the NFFT (Section 2: alpha_l from beta_k by the
+// inverse Fourier matrix, and its conjugate transpose in the adjoint): W
+// lines of length L are staged in LDS, transformed by a Stockham autosort FFT
+// with radices 8, 4, 2, 3, 5 (ping-pong between two LDS buffers, one barrier
+// per stage), and written back.  Input rows fill only part of each line
+// (zero padding of the small grid n into sigma n) and only the needed output
+// rows are stored (pruning of the grid to the region the window touches).
+// Pass A of the forward transform also applies the deconvolution
+// 1 / prod_j phi_j(kappa_j) (Lemma 2.6) to its input, and pass A of the
+// adjoint applies it to its output.
+#include "sgl_internal.h"
+
+namespace sgl {
+
+namespace {
+
+// y[a] = sum_b x[b] e^{sign 2 pi i a b / RAD}
+template <class R>
+__device__ inline cplx<R> mul_si(cplx<R> x, int sign) {  // x * (sign * i)
+  return sign > 0 ? cplx<R>{-x.im, x.re} : cplx<R>{x.im, -x.re};
+}
+
+template <class R, int RAD>
+struct Dft;
+
+template <class R>
+struct Dft<R, 2> {
+  __device__ static void run(cplx<R> *v, int) {
+    const cplx<R> a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  }
+};
+
+template <class R>
+struct Dft<R, 4> {
+  __device__ static void run(cplx<R> *v, int s) {
+    const cplx<R> a = cadd(v[0], v[2]), b = csub(v[0], v[2]);
+    const cplx<R> c = cadd(v[1], v[3]), d = mul_si(csub(v[1], v[3]), s);
+    v[0] = cadd(a, c);
+    v[2] = csub(a, c);
+    v[1] = cadd(b, d);
+    v[3] = csub(b, d);
+  }
+};
+
+template <class R>
+struct Dft<R, 8> {
+  __device__ static void run(cplx<R> *v, int s) {
+    cplx<R> e[4] = {v[0], v[2], v[4], v[6]};
+    cplx<R> o[4] = {v[1], v[3], v[5], v[7]};
+    Dft<R, 4>::run(e, s);
+    Dft<R, 4>::run(o, s);
+    const R h = (R)0.70710678118654752440084436210484903928;
+    // o[k] *= e^{s i pi k / 4}
+    const cplx<R> o1 = {(o[1].re - s * o[1].im) * h, (o[1].im + s * o[1].re) * h};
+    const cplx<R> o2 = mul_si(o[2], s);
+    const cplx<R> o3 = {(-o[3].re - s * o[3].im) * h, (-o[3].im + s * o[3].re) * h};
+    v[0] = cadd(e[0], o[0]);
+    v[4] = csub(e[0], o[0]);
+    v[1] = cadd(e[1], o1);
+    v[5] = csub(e[1], o1);
+    v[2] = cadd(e[2], o2);
+    v[6] = csub(e[2], o2);
+    v[3] = cadd(e[3], o3);
+    v[7] = csub(e[3], o3);
+  }
+};
+
+template <class R>
+struct Dft<R, 3> {
+  __device__ static void run(cplx<R> *v, int s) {
+    const R c = (R)0.86602540378443864676372317075293618347;  // sqrt(3)/2
+    const cplx<R> t = cadd(v[1], v[2]);
+    const cplx<R> u = cscale(mul_si(csub(v[1], v[2]), s), c);
+    const cplx<R> m = {v[0].re - t.re / 2, v[0].im - t.im / 2};
+    v[0] = cadd(v[0], t);
+    v[1] = cadd(m, u);
+    v[2] = csub(m, u);
+  }
+};
+
+template <class R>
+struct Dft<R, 5> {
+  __device__ static void run(cplx<R> *v, int s) {
+    const R c1 = (R)0.30901699437494742410229341718281905886;   // cos(2 pi / 5)
+    const R c2 = (R)-0.80901699437494742410229341718281905886;  // cos(4 pi / 5)
+    const R s1 = (R)0.95105651629515357211643933337938214340;   // sin(2 pi / 5)
+    const R s2 = (R)0.58778525229247312916870595463907276860;   // sin(4 pi / 5)
+    const cplx<R> t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
+    const cplx<R> d1 = csub(v[1], v[4]), d2 = csub(v[2], v[3]);
+    const cplx<R> x0 = v[0];
+    const cplx<R> a1 = {x0.re + c1 * t1.re + c2 * t2.re, x0.im + c1 * t1.im + c2 * t2.im};
+    const cplx<R> a2 = {x0.re + c2 * t1.re + c1 * t2.re, x0.im + c2 * t1.im + c1 * t2.im};
+    const cplx<R> b1 = mul_si(cplx<R>{s1 * d1.re + s2 * d2.re, s1 * d1.im + s2 * d2.im}, s);
+    const cplx<R> b2 = mul_si(cplx<R>{s2 * d1.re - s1 * d2.re, s2 * d1.im - s1 * d2.im}, s);
+    v[0] = cadd(x0, cadd(t1, t2));
+    v[1] = cadd(a1, b1);
+    v[4] = csub(a1, b1);
+    v[2] = cadd(a2, b2);
+    v[3] = csub(a2, b2);
+  }
+};
+
+// One Stockham stage: Ns = product of the radices already applied.
+template <class R, int RAD>
+__device__ void stage(const cplx<R> *__restrict__ src, cplx<R> *__restrict__ dst, int L, int W, int Ns,
+                      const cplx<R> *__restrict__ tw, int sign) {
+  const int nb = (L / RAD) * W;
+  const int twstride = L / (Ns * RAD);
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+    const int w = b % W, j = b / W, k = j % Ns;
+    cplx<R> v[RAD];
+#pragma unroll
+    for (int r = 0; r < RAD; ++r) v[r] = src[(j + r * (L / RAD)) * W + w];
+    if (Ns > 1) {
+#pragma unroll
+      for (int r = 1; r < RAD; ++r) {
+        cplx<R> t = tw[r * k * twstride];
+        if (sign < 0) t.im = -t.im;
+        v[r] = cmul(v[r], t);
+      }
+    }
+    Dft<R, RAD>::run(v, sign);
+    const int idxD = (j / Ns) * Ns * RAD + k;
+#pragma unroll
+    for (int r = 0; r < RAD; ++r) dst[(idxD + r * Ns) * W + w] = v[r];
+  }
+}
+
+__device__ inline int wrap(int i, int L) {
+  i %= L;
+  return i < 0 ? i + L : i;
+}
+
+// dcmode: 0 none; 1 multiply input row i of line o by dc0[o / n1] dc1[o % n1]
+// dc2[i]; 2 the same on output rows (pass A of the forward / adjoint).
+template <class R>
+__global__ __launch_bounds__(256) void k_fft(const cplx<R> *__restrict__ in, cplx<R> *__restrict__ out, FftPass fp,
+                                             const cplx<R> *__restrict__ tw, const R *__restrict__ dc, int dcmode,
+                                             int n0, int n1) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const int L = fp.L, W = fp.W;
+  cplx<R> *buf0 = (cplx<R> *)smem;
+  cplx<R> *buf1 = buf0 + (size_t)L * W;
+
+  // line w of this workgroup -> (outer index o, inner index ic)
+  int o_base, ic_base;
+  if (fp.inner > 1) {
+    const int gpo = (fp.inner + W - 1) / W;
+    o_base = blockIdx.x / gpo;
+    ic_base = (blockIdx.x % gpo) * W;
+  } else {
+    o_base = blockIdx.x * W;
+    ic_base = 0;
+  }
+
+  for (int e = threadIdx.x; e < L * W; e += blockDim.x) buf0[e] = cplx<R>{0, 0};
+  __syncthreads();
+
+  for (int e = threadIdx.x; e < fp.nin * W; e += blockDim.x) {
+    int i, w;
+    if (fp.inner > 1) {
+      i = e / W;
+      w = e % W;
+    } else {
+      w = e / fp.nin;
+      i = e % fp.nin;
+    }
+    const int o = fp.inner > 1 ? o_base : o_base + w;
+    const int ic = fp.inner > 1 ? ic_base + w : 0;
+    if (o >= fp.outer || ic >= fp.inner) continue;
+    cplx<R> v = in[((size_t)o * fp.nin + i) * fp.inner + ic];
+    if (dcmode == 1) v = cscale(v, dc[o / n1] * dc[n0 + o % n1] * dc[n0 + n1 + i]);
+    buf0[wrap(fp.in_off + i, L) * W + w] = v;
+  }
+  __syncthreads();
+
+  cplx<R> *src = buf0, *dst = buf1;
+  int Ns = 1;
+  for (int s = 0; s < fp.nstages; ++s) {
+    const int rad = fp.radix[s];
+    switch (rad) {
+      case 8: stage<R, 8>(src, dst, L, W, Ns, tw, fp.sign); break;
+      case 4: stage<R, 4>(src, dst, L, W, Ns, tw, fp.sign); break;
+      case 2: stage<R, 2>(src, dst, L, W, Ns, tw, fp.sign); break;
+      case 3: stage<R, 3>(src, dst, L, W, Ns, tw, fp.sign); break;
+      default: stage<R, 5>(src, dst, L, W, Ns, tw, fp.sign); break;
+    }
+    __syncthreads();
+    cplx<R> *t = src;
+    src = dst;
+    dst = t;
+    Ns *= rad;
+  }
+
+  for (int e = threadIdx.x; e < fp.nout * W; e += blockDim.x) {
+    int i, w;
+    if (fp.inner > 1) {
+      i = e / W;
+      w = e % W;
+    } else {
+      w = e / fp.nout;
+      i = e % fp.nout;
+    }
+    const int o = fp.inner > 1 ? o_base : o_base + w;
+    const int ic = fp.inner > 1 ? ic_base + w : 0;
+    if (o >= fp.outer || ic >= fp.inner) continue;
+    cplx<R> v = src[wrap(fp.out_off + i, L) * W + w];
+    if (dcmode == 2) v = cscale(v, dc[o / n1] * dc[n0 + o % n1] * dc[n0 + n1 + i]);
+    out[((size_t)o * fp.nout + i) * fp.inner + ic] = v;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_fft_pass(const Plan &p, const FftPass &fp, const void *in, void *out, int tw_index, int dcmode,
+                           int /*unused*/) {
+  const int groups = fp.inner > 1 ? fp.outer * ((fp.inner + fp.W - 1) / fp.W) : (fp.outer + fp.W - 1) / fp.W;
+  if (p.prec == SGL_F64) {
+    const size_t lds = 2 * (size_t)fp.L * fp.W * sizeof(cplx<double>);
+    k_fft<double><<<groups, 256, lds, p.stream>>>((const cplx<double> *)in, (cplx<double> *)out, fp,
+                                                  (const cplx<double> *)p.twiddle + p.tw_off[tw_index],
+                                                  (const double *)p.deconv, dcmode, p.n[0], p.n[1]);
+  } else {
+    const size_t lds = 2 * (size_t)fp.L * fp.W * sizeof(cplx<float>);
+    k_fft<float><<<groups, 256, lds, p.stream>>>((const cplx<float> *)in, (cplx<float> *)out, fp,
+                                                 (const cplx<float> *)p.twiddle + p.tw_off[tw_index],
+                                                 (const float *)p.deconv, dcmode, p.n[0], p.n[1]);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace sgl

@@ -1,0 +1,509 @@
+// Windowed gather (the evaluation of s(t) of Section 2) and its adjoint
+// scatter, with the Gaussian window of Def. 2.5 truncated as in eq. nfft_psi.
+// With u_j = N_j t_j / (2 pi), the 2q taps per dimension are the integers l
+// with u_j - q < l <= u_j + q (base cell b = floor(u), taps b-q+1 .. b+q), and
+//     s(t) = sum_taps g[l mod N] prod_j exp(-(u_j - l_j)^2 / (2 lambda)),
+// where the constant (2 pi lambda)^{-3/2} has been moved into the
+// deconvolution factors applied in the FFT passes.
+//
+// The grid g is stored pruned: in dimensions 0 and 1 (angles in [0, pi])
+// only rows l in [1-q, N_j/2 + q] are kept (stored index l - lo), in
+// dimension 2 the whole period (stored index l mod N).
+//
+//  * gather (tiled): one workgroup per chunk of points of one tile of base
+//    cells; the tile's window box is staged in LDS and each thread evaluates
+//    one point at a time.
+//  * gather (direct): each thread evaluates one point reading the grid
+//    through the cache (used when the window box does not fit in LDS).
+//  * scatter: output-driven; each workgroup owns a block of stored cells,
+//    accumulates the contributions of every point whose taps reach the block
+//    in LDS, and writes the block once.  No global atomics; every cell of the
+//    grid is written by exactly one workgroup.
+#include "sgl_internal.h"
+
+namespace sgl {
+
+namespace {
+
+struct Geom {
+  int q;
+  int N[3], E[3], lo[3], pruned[3];
+  int L[3], T[3], X[3], NB[3];
+  int Lo[3], To[3];
+};
+
+__device__ inline int stored_index(int l, int j, const Geom &g) {
+  if (g.pruned[j]) {
+    const int s = l - g.lo[j];
+    return (s >= 0 && s < g.E[j]) ? s : -1;
+  }
+  int s = l % g.N[j];
+  return s < 0 ? s + g.N[j] : s;
+}
+
+template <class R>
+__device__ inline R gauss(R d, R inv2lam) {
+  return exp(-d * d * inv2lam);
+}
+
+// ---------------------------------------------------------------- gather, tiled
+
+template <class R, int Q2>
+__global__ __launch_bounds__(256) void k_gather_tiled(const cplx<R> *__restrict__ grid,
+                                                      const PointRec<R> *__restrict__ pts,
+                                                      const int32_t *__restrict__ perm,
+                                                      const int32_t *__restrict__ chunks, Geom g, R inv2lam,
+                                                      cplx<R> *__restrict__ f) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  cplx<R> *tile = (cplx<R> *)smem;
+  constexpr int q = Q2 / 2;
+  const int tidx = chunks[3 * blockIdx.x];
+  const int start = chunks[3 * blockIdx.x + 1];
+  const int count = chunks[3 * blockIdx.x + 2];
+  const int c2 = tidx % g.T[2];
+  const int c1 = (tidx / g.T[2]) % g.T[1];
+  const int c0 = tidx / (g.T[2] * g.T[1]);
+  const int X0 = g.X[0], X1 = g.X[1], X2 = g.X[2];
+  const int wb0 = c0 * g.L[0] - q + 1, wb1 = c1 * g.L[1] - q + 1, wb2 = c2 * g.L[2] - q + 1;
+  for (int e = threadIdx.x; e < X0 * X1 * X2; e += blockDim.x) {
+    const int i2 = e % X2, r = e / X2, i1 = r % X1, i0 = r / X1;
+    const int s0 = stored_index(wb0 + i0, 0, g), s1 = stored_index(wb1 + i1, 1, g),
+              s2 = stored_index(wb2 + i2, 2, g);
+    cplx<R> v = {0, 0};
+    if (s0 >= 0 && s1 >= 0 && s2 >= 0) v = grid[((size_t)s0 * g.E[1] + s1) * g.E[2] + s2];
+    tile[e] = v;
+  }
+  __syncthreads();
+  for (int k = start + threadIdx.x; k < start + count; k += blockDim.x) {
+    const PointRec<R> pr = pts[k];
+    const int o0 = cell0(pr.cell) - c0 * g.L[0];
+    const int o1 = cell1(pr.cell) - c1 * g.L[1];
+    const int o2 = cell2(pr.cell) - c2 * g.L[2];
+    R w1[Q2], w2[Q2];
+#pragma unroll
+    for (int t = 0; t < Q2; ++t) {
+      w1[t] = gauss<R>(pr.frac[1] + (R)(q - 1 - t), inv2lam);
+      w2[t] = gauss<R>(pr.frac[2] + (R)(q - 1 - t), inv2lam);
+    }
+    R ar = 0, ai = 0;
+    const cplx<R> *base = tile + ((size_t)o0 * X1 + o1) * X2 + o2;
+    for (int t0 = 0; t0 < Q2; ++t0) {
+      const R w0 = gauss<R>(pr.frac[0] + (R)(q - 1 - t0), inv2lam);
+      const cplx<R> *plane = base + (size_t)t0 * X1 * X2;
+      R br = 0, bi = 0;
+#pragma unroll
+      for (int t1 = 0; t1 < Q2; ++t1) {
+        const cplx<R> *row = plane + t1 * X2;
+        R cr = 0, ci = 0;
+#pragma unroll
+        for (int t2 = 0; t2 < Q2; ++t2) {
+          const cplx<R> v = row[t2];
+          cr += w2[t2] * v.re;
+          ci += w2[t2] * v.im;
+        }
+        br += w1[t1] * cr;
+        bi += w1[t1] * ci;
+      }
+      ar += w0 * br;
+      ai += w0 * bi;
+    }
+    f[perm[k]] = cplx<R>{ar, ai};
+  }
+}
+
+// ---------------------------------------------------------------- gather, direct
+
+template <class R, int Q2>
+__global__ __launch_bounds__(256) void k_gather_direct(const cplx<R> *__restrict__ grid,
+                                                       const PointRec<R> *__restrict__ pts,
+                                                       const int32_t *__restrict__ perm, int64_t M, Geom g,
+                                                       R inv2lam, cplx<R> *__restrict__ f) {
+  constexpr int q = Q2 / 2;
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= M) return;
+  const PointRec<R> pr = pts[k];
+  const int b0 = cell0(pr.cell), b1 = cell1(pr.cell), b2 = cell2(pr.cell);
+  R w2[Q2];
+  int i2[Q2];
+#pragma unroll
+  for (int t = 0; t < Q2; ++t) {
+    w2[t] = gauss<R>(pr.frac[2] + (R)(q - 1 - t), inv2lam);
+    i2[t] = stored_index(b2 - q + 1 + t, 2, g);
+  }
+  R ar = 0, ai = 0;
+  for (int t0 = 0; t0 < Q2; ++t0) {
+    const int s0 = stored_index(b0 - q + 1 + t0, 0, g);
+    const R w0 = gauss<R>(pr.frac[0] + (R)(q - 1 - t0), inv2lam);
+    R br = 0, bi = 0;
+    for (int t1 = 0; t1 < Q2; ++t1) {
+      const int s1 = stored_index(b1 - q + 1 + t1, 1, g);
+      const R w1 = gauss<R>(pr.frac[1] + (R)(q - 1 - t1), inv2lam);
+      const cplx<R> *row = grid + ((size_t)s0 * g.E[1] + s1) * g.E[2];
+      R cr = 0, ci = 0;
+#pragma unroll
+      for (int t2 = 0; t2 < Q2; ++t2) {
+        const cplx<R> v = row[i2[t2]];
+        cr += w2[t2] * v.re;
+        ci += w2[t2] * v.im;
+      }
+      br += w1 * cr;
+      bi += w1 * ci;
+    }
+    ar += w0 * br;
+    ai += w0 * bi;
+  }
+  f[perm[k]] = cplx<R>{ar, ai};
+}
+
+// ---------------------------------------------------------------- scatter
+
+// Taps t in [0, Q2) of a point with base cell b whose stored index falls in
+// the block [S, S + ext): at most two runs t in [tb, te) with block offset
+// ub + (t - tb).
+__device__ inline int tap_runs(int b, int S, int ext, int j, const Geom &g, int Q2, int *tb, int *te, int *ub) {
+  const int q = Q2 / 2;
+  if (g.pruned[j]) {
+    // stored index of tap t is b + t
+    const int lo = max(0, S - b), hi = min(Q2, S + ext - b);
+    if (lo >= hi) return 0;
+    tb[0] = lo;
+    te[0] = hi;
+    ub[0] = b + lo - S;
+    return 1;
+  }
+  const int N = g.N[j];
+  int d = (b - q + 1 - S) % N;  // block offset of tap 0, mod N
+  if (d < 0) d += N;
+  int n = 0;
+  const int a_hi = min(min(Q2, N - d), ext - d);
+  if (a_hi > 0) {
+    tb[n] = 0;
+    te[n] = a_hi;
+    ub[n] = d;
+    ++n;
+  }
+  const int b_lo = N - d, b_hi = min(Q2, ext + N - d);
+  if (b_lo < b_hi) {
+    tb[n] = b_lo;
+    te[n] = b_hi;
+    ub[n] = 0;
+    ++n;
+  }
+  return n;
+}
+
+constexpr int kMaxRows = 512;
+
+// Bins (tiles of base cells) in dimension j whose points can touch stored
+// cells [S, S + ext): merged disjoint bin intervals [first, last].
+__device__ inline int bin_ranges(int S, int ext, int j, const Geom &g, int *first, int *last) {
+  const int q = g.q, L = g.L[j], NB = g.NB[j];
+  int cand_lo[3], cand_hi[3], nc = 0;
+  if (g.pruned[j]) {
+    // stored s = b + t, t in [0, 2q)
+    const int lo = max(0, S - 2 * q + 1), hi = min(NB - 1, S + ext - 1);
+    if (lo <= hi) {
+      cand_lo[nc] = lo;
+      cand_hi[nc] = hi;
+      ++nc;
+    }
+  } else {
+    const int N = g.N[j];
+    const int blo = S - q, bhi = S + ext - 1 + q - 1;  // bases, modulo N
+    if (bhi - blo + 1 >= N) {
+      cand_lo[nc] = 0;
+      cand_hi[nc] = NB - 1;
+      ++nc;
+    } else {
+      for (int w = -1; w <= 1; ++w) {
+        const int lo = max(0, blo + w * N), hi = min(NB - 1, bhi + w * N);
+        if (lo <= hi) {
+          cand_lo[nc] = lo;
+          cand_hi[nc] = hi;
+          ++nc;
+        }
+      }
+    }
+  }
+  // to bins, then merge (candidates are increasing in base)
+  int n = 0;
+  for (int c = 0; c < nc; ++c) {
+    const int f0 = cand_lo[c] / L, l0 = cand_hi[c] / L;
+    if (n > 0 && f0 <= last[n - 1] + 0) {
+      if (l0 > last[n - 1]) last[n - 1] = l0;
+    } else {
+      first[n] = f0;
+      last[n] = l0;
+      ++n;
+    }
+  }
+  return n;
+}
+
+template <class R, int Q2>
+__global__ __launch_bounds__(256) void k_scatter(const cplx<R> *__restrict__ y, const PointRec<R> *__restrict__ pts,
+                                                 const int32_t *__restrict__ perm,
+                                                 const int32_t *__restrict__ tile_start, Geom g, R inv2lam,
+                                                 cplx<R> *__restrict__ grid) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  R *acc = (R *)smem;
+  __shared__ int row_start[kMaxRows];
+  __shared__ int row_pref[kMaxRows + 1];
+  __shared__ int nrows_s;
+  constexpr int q = Q2 / 2;
+  const int C2 = blockIdx.x % g.To[2];
+  const int C1 = (blockIdx.x / g.To[2]) % g.To[1];
+  const int C0 = blockIdx.x / (g.To[2] * g.To[1]);
+  const int S0 = C0 * g.Lo[0], S1 = C1 * g.Lo[1], S2 = C2 * g.Lo[2];
+  const int ext0 = min(g.Lo[0], g.E[0] - S0), ext1 = min(g.Lo[1], g.E[1] - S1), ext2 = min(g.Lo[2], g.E[2] - S2);
+  const int ncell = g.Lo[0] * g.Lo[1] * g.Lo[2];
+  for (int e = threadIdx.x; e < 2 * ncell; e += blockDim.x) acc[e] = 0;
+  if (threadIdx.x == 0) {
+    int f0[3], l0[3], f1[3], l1[3], f2[3], l2[3];
+    const int n0 = bin_ranges(S0, ext0, 0, g, f0, l0);
+    const int n1 = bin_ranges(S1, ext1, 1, g, f1, l1);
+    const int n2 = bin_ranges(S2, ext2, 2, g, f2, l2);
+    int nr = 0, tot = 0;
+    for (int a = 0; a < n0; ++a)
+      for (int x0 = f0[a]; x0 <= l0[a]; ++x0)
+        for (int b = 0; b < n1; ++b)
+          for (int x1 = f1[b]; x1 <= l1[b]; ++x1)
+            for (int c = 0; c < n2; ++c) {
+              const int t0 = (x0 * g.T[1] + x1) * g.T[2];
+              const int s = tile_start[t0 + f2[c]], e = tile_start[t0 + l2[c] + 1];
+              if (e > s && nr < kMaxRows) {
+                row_start[nr] = s;
+                row_pref[nr] = tot;
+                tot += e - s;
+                ++nr;
+              }
+            }
+    row_pref[nr] = tot;
+    nrows_s = nr;
+  }
+  __syncthreads();
+  const int nr = nrows_s;
+  const int total = row_pref[nr];
+  for (int gidx = threadIdx.x; gidx < total; gidx += blockDim.x) {
+    int lo = 0, hi = nr - 1;
+    while (lo < hi) {  // last row with row_pref <= gidx
+      const int mid = (lo + hi + 1) / 2;
+      if (row_pref[mid] <= gidx) lo = mid; else hi = mid - 1;
+    }
+    const int k = row_start[lo] + (gidx - row_pref[lo]);
+    const PointRec<R> pr = pts[k];
+    const int b0 = cell0(pr.cell), b1 = cell1(pr.cell), b2 = cell2(pr.cell);
+    int tb0[2], te0[2], ub0[2], tb1[2], te1[2], ub1[2], tb2[2], te2[2], ub2[2];
+    const int r0 = tap_runs(b0, S0, ext0, 0, g, Q2, tb0, te0, ub0);
+    if (!r0) continue;
+    const int r1 = tap_runs(b1, S1, ext1, 1, g, Q2, tb1, te1, ub1);
+    if (!r1) continue;
+    const int r2 = tap_runs(b2, S2, ext2, 2, g, Q2, tb2, te2, ub2);
+    if (!r2) continue;
+    const cplx<R> yv = y[perm[k]];
+    // Gaussian weights along a run by the recurrence w(t+1) = w(t) r(t),
+    // r(t+1) = r(t) c, with r(t) = exp((2 d_t - 1) / (2 lambda)), c = exp(-1/lambda),
+    // d_t = frac + q - 1 - t; carried in double.
+    const double il = (double)inv2lam;
+    const double cc = exp(-2.0 * il);
+    for (int i0 = 0; i0 < r0; ++i0) {
+      double d0 = (double)pr.frac[0] + (q - 1 - tb0[i0]);
+      double w0 = exp(-d0 * d0 * il), q0 = exp((2.0 * d0 - 1.0) * il);
+      for (int t0 = tb0[i0]; t0 < te0[i0]; ++t0) {
+        const int u0 = ub0[i0] + t0 - tb0[i0];
+        for (int i1 = 0; i1 < r1; ++i1) {
+          double d1 = (double)pr.frac[1] + (q - 1 - tb1[i1]);
+          double w1 = exp(-d1 * d1 * il), q1 = exp((2.0 * d1 - 1.0) * il);
+          for (int t1 = tb1[i1]; t1 < te1[i1]; ++t1) {
+            const int u1 = ub1[i1] + t1 - tb1[i1];
+            const double w01 = w0 * w1;
+            const R yr = (R)(yv.re * w01), yi = (R)(yv.im * w01);
+            R *rowacc = acc + 2 * ((u0 * g.Lo[1] + u1) * g.Lo[2]);
+            for (int i2 = 0; i2 < r2; ++i2) {
+              const double d2 = (double)pr.frac[2] + (q - 1 - tb2[i2]);
+              double w2 = exp(-d2 * d2 * il), q2 = exp((2.0 * d2 - 1.0) * il);
+              int u2 = ub2[i2];
+              for (int t2 = tb2[i2]; t2 < te2[i2]; ++t2, ++u2) {
+                const R wr = (R)w2;
+                atomicAdd(rowacc + 2 * u2, yr * wr);
+                atomicAdd(rowacc + 2 * u2 + 1, yi * wr);
+                w2 *= q2;
+                q2 *= cc;
+              }
+            }
+            w1 *= q1;
+            q1 *= cc;
+          }
+        }
+        w0 *= q0;
+        q0 *= cc;
+      }
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < ext0 * ext1 * ext2; e += blockDim.x) {
+    const int u2 = e % ext2, r = e / ext2, u1 = r % ext1, u0 = r / ext1;
+    const int c = (u0 * g.Lo[1] + u1) * g.Lo[2] + u2;
+    grid[((size_t)(S0 + u0) * g.E[1] + (S1 + u1)) * g.E[2] + (S2 + u2)] = cplx<R>{acc[2 * c], acc[2 * c + 1]};
+  }
+}
+
+// ---------------------------------------------------------------- exact NDFT
+
+// p(t_i) = sum_{k in I_n} eta_k e^{i <k, t_i>}, directly (Def. 2.4).
+template <class R>
+__global__ __launch_bounds__(256) void k_ndft(const cplx<R> *__restrict__ eta, const double *__restrict__ t, int64_t M,
+                                              int n0, int n1, int n2, cplx<R> *__restrict__ f) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= M) return;
+  const double t0 = t[i], t1 = t[M + i], t2 = t[2 * M + i];
+  double ar = 0, ai = 0;
+  for (int a = 0; a < n0; ++a) {
+    double s0, c0;
+    sincos((a - n0 / 2) * t0, &s0, &c0);
+    double br = 0, bi = 0;
+    for (int b = 0; b < n1; ++b) {
+      double s1, c1;
+      sincos((b - n1 / 2) * t1, &s1, &c1);
+      const cplx<R> *row = eta + ((size_t)a * n1 + b) * n2;
+      double cr = 0, ci = 0;
+      for (int c = 0; c < n2; ++c) {
+        double s2, c2;
+        sincos((c - n2 / 2) * t2, &s2, &c2);
+        const double er = row[c].re, ei = row[c].im;
+        cr += er * c2 - ei * s2;
+        ci += er * s2 + ei * c2;
+      }
+      br += cr * c1 - ci * s1;
+      bi += cr * s1 + ci * c1;
+    }
+    ar += br * c0 - bi * s0;
+    ai += br * s0 + bi * c0;
+  }
+  f[i] = cplx<R>{(R)ar, (R)ai};
+}
+
+template <class R>
+__global__ __launch_bounds__(256) void k_ndft_adj(const cplx<R> *__restrict__ y, const double *__restrict__ t,
+                                                  int64_t M, int n0, int n1, int n2, cplx<R> *__restrict__ eta) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= (int64_t)n0 * n1 * n2) return;
+  const int c = (int)(e % n2), b = (int)((e / n2) % n1), a = (int)(e / ((int64_t)n1 * n2));
+  const int k0 = a - n0 / 2, k1 = b - n1 / 2, k2 = c - n2 / 2;
+  double ar = 0, ai = 0;
+  for (int64_t i = 0; i < M; ++i) {
+    double s, co;
+    sincos(-(k0 * t[i] + k1 * t[M + i] + k2 * t[2 * M + i]), &s, &co);
+    const double yr = y[i].re, yi = y[i].im;
+    ar += yr * co - yi * s;
+    ai += yr * s + yi * co;
+  }
+  eta[e] = cplx<R>{(R)ar, (R)ai};
+}
+
+Geom make_geom(const Plan &p) {
+  Geom g;
+  g.q = p.q;
+  for (int j = 0; j < 3; ++j) {
+    g.N[j] = p.N[j];
+    g.E[j] = p.E[j];
+    g.lo[j] = p.lo[j];
+    g.pruned[j] = p.pruned[j] ? 1 : 0;
+    g.L[j] = p.L[j];
+    g.T[j] = p.T[j];
+    g.X[j] = p.X[j];
+    g.NB[j] = p.NB[j];
+    g.Lo[j] = p.Lo[j];
+    g.To[j] = p.To[j];
+  }
+  return g;
+}
+
+template <class R, int Q2>
+hipError_t gather_q(const Plan &p, const void *grid, void *f) {
+  const Geom g = make_geom(p);
+  const R inv2lam = (R)(1.0 / (2.0 * p.lambda));
+  if (p.gather_mode == 0) {
+    const size_t lds = (size_t)p.X[0] * p.X[1] * p.X[2] * sizeof(cplx<R>);
+    k_gather_tiled<R, Q2><<<(unsigned)p.nchunks, 256, lds, p.stream>>>(
+        (const cplx<R> *)grid, (const PointRec<R> *)p.pts, p.perm, p.chunks, g, inv2lam, (cplx<R> *)f);
+  } else {
+    k_gather_direct<R, Q2><<<(unsigned)((p.M + 255) / 256), 256, 0, p.stream>>>(
+        (const cplx<R> *)grid, (const PointRec<R> *)p.pts, p.perm, p.M, g, inv2lam, (cplx<R> *)f);
+  }
+  return hipGetLastError();
+}
+
+template <class R, int Q2>
+hipError_t scatter_q(const Plan &p, const void *f, void *grid) {
+  const Geom g = make_geom(p);
+  const R inv2lam = (R)(1.0 / (2.0 * p.lambda));
+  const size_t lds = 2 * (size_t)p.Lo[0] * p.Lo[1] * p.Lo[2] * sizeof(R);
+  k_scatter<R, Q2><<<(unsigned)p.nblocks, 256, lds, p.stream>>>((const cplx<R> *)f, (const PointRec<R> *)p.pts,
+                                                                p.perm, p.tile_start, g, inv2lam, (cplx<R> *)grid);
+  return hipGetLastError();
+}
+
+#define SGL_Q_CASES(F, R, ...)                 \
+  switch (p.q) {                               \
+    case 1: return F<R, 2>(__VA_ARGS__);       \
+    case 2: return F<R, 4>(__VA_ARGS__);       \
+    case 3: return F<R, 6>(__VA_ARGS__);       \
+    case 4: return F<R, 8>(__VA_ARGS__);       \
+    case 5: return F<R, 10>(__VA_ARGS__);      \
+    case 6: return F<R, 12>(__VA_ARGS__);      \
+    case 7: return F<R, 14>(__VA_ARGS__);      \
+    case 8: return F<R, 16>(__VA_ARGS__);      \
+    case 9: return F<R, 18>(__VA_ARGS__);      \
+    case 10: return F<R, 20>(__VA_ARGS__);     \
+    case 11: return F<R, 22>(__VA_ARGS__);     \
+    case 12: return F<R, 24>(__VA_ARGS__);     \
+    case 13: return F<R, 26>(__VA_ARGS__);     \
+    case 14: return F<R, 28>(__VA_ARGS__);     \
+    case 15: return F<R, 30>(__VA_ARGS__);     \
+    case 16: return F<R, 32>(__VA_ARGS__);     \
+    default: return hipErrorInvalidValue;      \
+  }
+
+}  // namespace
+
+hipError_t launch_gather(const Plan &p, const void *grid, void *f) {
+  if (p.prec == SGL_F64) {
+    SGL_Q_CASES(gather_q, double, p, grid, f)
+  } else {
+    SGL_Q_CASES(gather_q, float, p, grid, f)
+  }
+}
+
+hipError_t launch_scatter(const Plan &p, const void *f, void *grid) {
+  if (p.prec == SGL_F64) {
+    SGL_Q_CASES(scatter_q, double, p, f, grid)
+  } else {
+    SGL_Q_CASES(scatter_q, float, p, f, grid)
+  }
+}
+
+hipError_t launch_ndft_forward(const Plan &p, const void *eta, void *f) {
+  const int nb = (int)((p.M + 255) / 256);
+  if (p.prec == SGL_F64)
+    k_ndft<double><<<nb, 256, 0, p.stream>>>((const cplx<double> *)eta, (const double *)p.ptsxyz, p.M, p.n[0],
+                                             p.n[1], p.n[2], (cplx<double> *)f);
+  else
+    k_ndft<float><<<nb, 256, 0, p.stream>>>((const cplx<float> *)eta, (const double *)p.ptsxyz, p.M, p.n[0],
+                                            p.n[1], p.n[2], (cplx<float> *)f);
+  return hipGetLastError();
+}
+
+hipError_t launch_ndft_adjoint(const Plan &p, const void *f, void *eta) {
+  const int64_t ne = (int64_t)p.n[0] * p.n[1] * p.n[2];
+  const int nb = (int)((ne + 255) / 256);
+  if (p.prec == SGL_F64)
+    k_ndft_adj<double><<<nb, 256, 0, p.stream>>>((const cplx<double> *)f, (const double *)p.ptsxyz, p.M, p.n[0],
+                                                 p.n[1], p.n[2], (cplx<double> *)eta);
+  else
+    k_ndft_adj<float><<<nb, 256, 0, p.stream>>>((const cplx<float> *)f, (const double *)p.ptsxyz, p.M, p.n[0],
+                                                p.n[1], p.n[2], (cplx<float> *)eta);
+  return hipGetLastError();
+}
+
+}  // namespace sgl

@@ -1,0 +1,249 @@
+"""GPU parity: the HIP path through the C-ABI against the oracle.
+
+* stage pins (FP64, roundoff level): the conversion against the paper's
+  stepwise factorization, the NFFT against the stepwise Gaussian NFFT, the
+  exact-NDFT mode against the direct sum;
+* end to end against the direct sum (Def. 1.3) within the NFFT tolerance;
+* the adjoint identity <Lambda fhat, y> = <fhat, Lambda^H y> of the fast pair;
+* edge cases: origin, z axis, phi near 2 pi, r = rho, M = 1, B = 2, user rho,
+  and the documented error codes.
+Tolerances: FP64 stage pins 1e-11 (relative l2); FP64 end to end at q=16
+1e-9 (the paper reports ~1e-10 at q=16, Section 8); FP32 end to end 1e-5.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import stepwise as sw
+from tests import workloads as wl
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _sgl():
+    import paper_1809_10786_amd as sgl
+
+    return sgl
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def relinf(a, b):
+    return float(np.abs(np.asarray(a) - np.asarray(b)).max() / np.abs(np.asarray(b)).max())
+
+
+def dev(x, dtype):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(device="cuda", dtype=dtype)
+
+
+def plan(pts, B, prec="f64", q=6, **kw):
+    rdt = torch.float64 if prec == "f64" else torch.float32
+    return _sgl().Plan(dev(pts, rdt), B, q=q, precision=prec, **kw)
+
+
+def cdt(prec):
+    return torch.complex128 if prec == "f64" else torch.complex64
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy().astype(np.complex128)
+
+
+def pts_used(pts, prec):
+    """Points exactly as the library sees them (FP32 inputs promoted to FP64)."""
+    return pts.astype(np.float32).astype(np.float64) if prec == "f32" else pts
+
+
+# ------------------------------------------------------------ exact NDFT mode
+
+
+@pytest.mark.parametrize("B", [2, 3, 8])
+def test_exact_ndft_matches_direct_sum(B):
+    say(f"exact-ndft B={B} M=500 seed={B}")
+    pts = wl.gaussian_points(500, B)
+    fh = wl.coefficients(B, 100 + B)
+    p = plan(pts, B, exact_ndft=True)
+    f = host(p.forward(dev(fh, torch.complex128)))
+    f0 = oracle.direct_forward(B, pts, fh)
+    assert rel(f, f0) < 1e-12
+    y = wl.samples(500, 200 + B)
+    g = host(p.adjoint(dev(y, torch.complex128)))
+    g0 = oracle.direct_adjoint(B, pts, y)
+    assert rel(g, g0) < 1e-12
+
+
+def test_exact_ndft_fp32():
+    B = 8
+    say(f"exact-ndft fp32 B={B} M=500")
+    pts = wl.gaussian_points(500, 7)
+    fh = wl.coefficients(B, 8)
+    p = plan(pts, B, prec="f32", exact_ndft=True)
+    f = host(p.forward(dev(fh, torch.complex64)))
+    f0 = oracle.direct_forward(B, pts_used(pts, "f32"), fh.astype(np.complex64).astype(np.complex128))
+    assert rel(f, f0) < 1e-5
+
+
+# ------------------------------------------------------------ stage pins
+
+
+@pytest.mark.parametrize("B", [2, 5, 8, 12])
+def test_conversion_stage_matches_stepwise(B):
+    say(f"conv stage B={B}")
+    pts = wl.gaussian_points(300, 10 + B)
+    fh = wl.coefficients(B, 11 + B)
+    p = plan(pts, B)
+    eta = host(p.conv_forward(dev(fh, torch.complex128))).reshape(p.eta_shape)
+    eta0 = sw.conversion(B, fh, p.rho, reduced=True)
+    assert rel(eta, eta0) < 1e-12
+    e = np.random.default_rng(B).standard_normal(p.eta_shape) * (1 + 0.5j)
+    g = host(p.conv_adjoint(dev(e, torch.complex128)))
+    g0 = sw.conversion_adjoint(B, e, p.rho)
+    assert rel(g, g0) < 1e-12
+
+
+@pytest.mark.parametrize("B,q", [(4, 3), (8, 6), (8, 16), (12, 5)])
+def test_nfft_stage_matches_stepwise(B, q):
+    say(f"nfft stage B={B} q={q}")
+    pts = wl.gaussian_points(700, 20 + B)
+    p = plan(pts, B, q=q)
+    rng = np.random.default_rng(30 + B)
+    eta = (rng.standard_normal(p.eta_shape) + 1j * rng.standard_normal(p.eta_shape))
+    f = host(p.nfft_forward(dev(eta, torch.complex128)))
+    t = sw.x_tilde(pts, p.rho)
+    f0 = sw.nfft(eta, t, 2, q)
+    assert rel(f, f0) < 1e-11
+    y = wl.samples(700, 40 + B)
+    e = host(p.nfft_adjoint(dev(y, torch.complex128))).reshape(p.eta_shape)
+    e0 = sw.nfft_adjoint(y, t, p.eta_shape, 2, q)
+    assert rel(e, e0) < 1e-11
+
+
+# ------------------------------------------------------------ end to end
+
+
+def test_b8_m1e4_f64_against_direct_sum():
+    """Plain FP64 forward and adjoint, B=8, M=1e4, q=16."""
+    w, pts, fh, y = wl.workload("b8_m1e4_f64", seed=1)
+    say(f"e2e {w}")
+    p = plan(pts, w["B"], q=w["q"])
+    f = host(p.forward(dev(fh, torch.complex128)))
+    f0 = oracle.direct_forward(w["B"], pts, fh)
+    assert rel(f, f0) < 1e-9 and relinf(f, f0) < 1e-9
+    g = host(p.adjoint(dev(y, torch.complex128)))
+    g0 = oracle.direct_adjoint(w["B"], pts, y)
+    assert rel(g, g0) < 1e-9 and relinf(g, g0) < 1e-9
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 2e-6), ("f32", 1e-5)])
+def test_b32_mixed_points_subset(prec, tol):
+    """B=32 at q=6 on the mixed point set (1e5 points of the workload)."""
+    w, pts, fh, y = wl.workload("b32_m1e6_" + prec, seed=2, M=100_000)
+    say(f"e2e b32 {prec} M={len(pts)}")
+    p = plan(pts, 32, prec=prec, q=6)
+    pu = pts_used(pts, prec)
+    fhu = fh.astype(np.complex64).astype(np.complex128) if prec == "f32" else fh
+    f = host(p.forward(dev(fh, cdt(prec))))
+    sample = np.random.default_rng(3).choice(len(pts), 4000, replace=False)
+    f0 = oracle.direct_forward(32, pu[sample], fhu)
+    assert rel(f[sample], f0) < tol
+    assert relinf(f[sample], f0) < tol
+    # adjoint on samples supported on a subset: Lambda^H restricted to it
+    ys = np.zeros(len(pts), dtype=np.complex128)
+    ys[sample] = y[sample]
+    ysu = ys.astype(np.complex64).astype(np.complex128) if prec == "f32" else ys
+    g = host(p.adjoint(dev(ys, cdt(prec))))
+    g0 = oracle.direct_adjoint(32, pu[sample], ysu[sample])
+    assert rel(g, g0) < tol
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-12), ("f32", 2e-6)])
+def test_adjoint_identity(prec, tol):
+    B = 16
+    say(f"dot test B={B} {prec}")
+    pts = wl.mixed_points(20_000, 5)
+    fh = wl.coefficients(B, 6)
+    y = wl.samples(20_000, 7)
+    p = plan(pts, B, prec=prec, q=6)
+    f = host(p.forward(dev(fh, cdt(prec))))
+    g = host(p.adjoint(dev(y, cdt(prec))))
+    fhu = fh.astype(np.complex64).astype(np.complex128) if prec == "f32" else fh
+    yu = y.astype(np.complex64).astype(np.complex128) if prec == "f32" else y
+    lhs, rhs = np.vdot(yu, f), np.vdot(g, fhu)
+    assert abs(lhs - rhs) < tol * np.linalg.norm(yu) * np.linalg.norm(f)
+
+
+def test_gather_is_deterministic():
+    B = 16
+    pts = wl.gaussian_points(50_000, 8)
+    fh = wl.coefficients(B, 9)
+    p = plan(pts, B, prec="f32")
+    a = host(p.forward(dev(fh, torch.complex64)))
+    b = host(p.forward(dev(fh, torch.complex64)))
+    assert np.array_equal(a, b)
+
+
+# ------------------------------------------------------------ edge cases
+
+
+def test_edge_points():
+    """Origin, both poles, points on the z axis, phi just below 2 pi, r = rho."""
+    B = 8
+    pts = np.array([[0, 0, 0], [0, 0, 1.3], [0, 0, -0.7], [2.0, 0, 0], [1.0, -1e-17, 0.3],
+                    [0.5, -1e-9, -0.2], [0, 0, 3.0], [1e-300, 0, 0], [-1.5, 0, 0.0]], dtype=np.float64)
+    pts = np.concatenate([pts, wl.gaussian_points(200, 11)])
+    fh = wl.coefficients(B, 12)
+    say("edge points")
+    for q, tol in ((16, 1e-9), (6, 2e-6)):
+        p = plan(pts, B, q=q)
+        assert p.rho == pytest.approx(np.linalg.norm(pts, axis=1).max())
+        f = host(p.forward(dev(fh, torch.complex128)))
+        f0 = oracle.direct_forward(B, pts, fh)
+        assert relinf(f, f0) < tol
+        y = wl.samples(len(pts), 13)
+        g = host(p.adjoint(dev(y, torch.complex128)))
+        assert rel(g, oracle.direct_adjoint(B, pts, y)) < tol
+
+
+def test_single_point_and_smallest_bandwidth():
+    say("M=1, B=2")
+    pts = np.array([[0.3, -0.4, 0.5]])
+    for B in (2, 3):
+        fh = wl.coefficients(B, 14)
+        p = plan(pts, B, q=4)
+        f = host(p.forward(dev(fh, torch.complex128)))
+        f0 = oracle.direct_forward(B, pts, fh)
+        assert abs(f[0] - f0[0]) < 1e-3 * abs(f0[0]) + 1e-12
+        pe = plan(pts, B, exact_ndft=True)
+        assert abs(host(pe.forward(dev(fh, torch.complex128)))[0] - f0[0]) < 1e-13
+
+
+def test_user_rho_and_errors():
+    B = 8
+    pts = wl.gaussian_points(1000, 15)
+    fh = wl.coefficients(B, 16)
+    say("user rho")
+    p = plan(pts, B, q=16, rho=5.0)
+    assert p.rho == 5.0
+    f = host(p.forward(dev(fh, torch.complex128)))
+    assert rel(f, oracle.direct_forward(B, pts, fh)) < 1e-8
+    sgl = _sgl()
+    with pytest.raises(sgl.SglError) as e:
+        plan(pts, B, rho=0.5)
+    assert e.value.status == sgl.SGL_E_RANGE
+    bad = pts.copy()
+    bad[17, 1] = np.nan
+    with pytest.raises(sgl.SglError) as e:
+        plan(bad, B)
+    assert e.value.status == sgl.SGL_E_INVAL
+    # aliasing input/output is rejected before any work
+    x = dev(np.zeros(max(sgl.num_coeffs(B), 1000), dtype=np.complex128), torch.complex128)
+    st = sgl.lib().sgl_forward(p._h, x.data_ptr(), x.data_ptr())
+    assert st == sgl.SGL_E_INVAL
