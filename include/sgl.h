@@ -133,7 +133,8 @@ sgl_status sgl_plan_info(sgl_plan_t plan, int64_t info[12]);
 /* Stages timed by the optional per-stage profiler (forward: radial and polar
  * conversion, FFT passes A (along m), B (along k1), C (along k0), gather;
  * adjoint: scatter, FFT passes C, B, A, polar and radial adjoint conversion;
- * exact mode: NDFT and its adjoint). */
+ * exact mode: NDFT and its adjoint; fold: summation of the staged window
+ * boxes of the tiled scatter into the grid). */
 enum {
   SGL_STAGE_CONV_RADIAL = 0,
   SGL_STAGE_CONV_POLAR,
@@ -149,6 +150,7 @@ enum {
   SGL_STAGE_CONV_RADIAL_ADJ,
   SGL_STAGE_NDFT,
   SGL_STAGE_NDFT_ADJ,
+  SGL_STAGE_FOLD,
   SGL_NUM_STAGES
 };
 

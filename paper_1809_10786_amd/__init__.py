@@ -23,7 +23,7 @@ SYMBOLS = (
 )
 
 STAGES = ("conv_radial", "conv_polar", "fft_A", "fft_B", "fft_C", "gather", "scatter", "fft_Ch", "fft_Bh",
-          "fft_Ah", "conv_polar_adj", "conv_radial_adj", "ndft", "ndft_adj")
+          "fft_Ah", "conv_polar_adj", "conv_radial_adj", "ndft", "ndft_adj", "fold")
 
 
 class SglParams(ctypes.Structure):

@@ -54,8 +54,8 @@ int lines_per_group(int L, size_t elem) {
 }
 
 void free_plan(Plan &p) {
-  void *bufs[] = {p.pts, p.perm, p.tile_start, p.chunks, p.krad, p.kpol, p.deconv, p.twiddle,
-                  p.beta, p.eta, p.bufX, p.bufY, p.ptsxyz};
+  void *bufs[] = {p.pts, p.perm, p.tile_start, p.chunks, p.krad, p.kpol, p.deconv, p.twiddle, p.beta,
+                  p.zeta, p.eta, p.bufX, p.bufY, p.ptsxyz, p.tile_chunk, p.staging};
   for (void *b : bufs)
     if (b) hipFree(b);
 }
@@ -137,6 +137,10 @@ sgl_status setup_geometry(Plan &p) {
     L[j] /= 2;
   }
   p.gather_mode = box(L) <= kLdsBudget ? 0 : 1;
+  // the row-register spreading of the tiled scatter needs one thread per box
+  // row (at most 512) and a box edge of 4 or 8 base cells along dimension 2
+  if ((size_t)(L[0] + 2 * p.q - 1) * (L[1] + 2 * p.q - 1) > 512 || p.q > 8 || (L[2] != 4 && L[2] != 8))
+    p.gather_mode = 1;
   p.ntiles = 1;
   for (int j = 0; j < 3; ++j) {
     p.L[j] = std::min(L[j], p.NB[j]);
@@ -189,8 +193,8 @@ sgl_status build_tables(Plan &p) {
   build_radial_table(p.B, p.rho, kr, p.krad_off);
   build_polar_table(p.B, kp, p.kpol_off);
   build_deconv(p, dc);
-  SGL_TRY(upload_real<R>(p, &p.krad, kr));
-  SGL_TRY(upload_real<R>(p, &p.kpol, kp));
+  SGL_TRY(upload_real<double>(p, &p.krad, kr));
+  SGL_TRY(upload_real<double>(p, &p.kpol, kp));
   SGL_TRY(upload_real<R>(p, &p.deconv, dc));
   SGL_TRY(upload_twiddles<R>(p));
   return SGL_OK;
@@ -243,17 +247,24 @@ sgl_status make_plan(Plan &p, const void *points) {
   // 4. gather work list: chunks of at most kChunk points of one tile
   std::vector<int32_t> ts(p.ntiles + 1);
   SGL_TRY(hipMemcpy(ts.data(), p.tile_start, ts.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
-  const int kChunk = 512;
-  std::vector<int32_t> ch;
-  for (int64_t t = 0; t < p.ntiles; ++t)
+  const int kChunk = 1024;
+  std::vector<int32_t> ch, tc(p.ntiles + 1);
+  for (int64_t t = 0; t < p.ntiles; ++t) {
+    tc[t] = (int32_t)(ch.size() / 3);
     for (int s = ts[t]; s < ts[t + 1]; s += kChunk) {
       ch.push_back((int32_t)t);
       ch.push_back(s);
       ch.push_back(std::min(kChunk, ts[t + 1] - s));
     }
+  }
+  tc[p.ntiles] = (int32_t)(ch.size() / 3);
   p.nchunks = (int64_t)ch.size() / 3;
   SGL_TRY(dev_alloc(p, &p.chunks, ch.size() * sizeof(int32_t)));
   if (!ch.empty()) SGL_TRY(hipMemcpy(p.chunks, ch.data(), ch.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  SGL_TRY(dev_alloc(p, &p.tile_chunk, tc.size() * sizeof(int32_t)));
+  SGL_TRY(hipMemcpy(p.tile_chunk, tc.data(), tc.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  if (p.gather_mode == 0)
+    SGL_TRY(dev_alloc(p, &p.staging, (size_t)p.nchunks * p.X[0] * p.X[1] * p.X[2] * cbytes(p)));
   // 5. tables
   st = p.prec == SGL_F64 ? build_tables<double>(p) : build_tables<float>(p);
   if (st != SGL_OK) return st;
@@ -265,7 +276,8 @@ sgl_status make_plan(Plan &p, const void *points) {
   const size_t nT1 = (size_t)p.n[0] * p.n[1] * p.N[2];
   const size_t nT2 = (size_t)p.n[0] * p.E[1] * p.N[2];
   const size_t nG = (size_t)p.E[0] * p.E[1] * p.E[2];
-  SGL_TRY(dev_alloc(p, &p.beta, nbeta * cb));
+  SGL_TRY(dev_alloc(p, &p.beta, nbeta * 16));
+  SGL_TRY(dev_alloc(p, &p.zeta, (size_t)(2 * B - 1) * B * (2 * B - 1) * 16));  // compact zeta
   SGL_TRY(dev_alloc(p, &p.eta, neta * cb));
   SGL_TRY(dev_alloc(p, &p.bufX, std::max(nT1, nG) * cb));
   SGL_TRY(dev_alloc(p, &p.bufY, nT2 * cb));
@@ -340,6 +352,7 @@ sgl_status nfft_adj(Plan &p, const void *f, void *eta) {
     return SGL_OK;
   }
   SGL_STAGE(SGL_STAGE_SCATTER, launch_scatter(p, f, p.bufX));
+  if (p.gather_mode == 0) SGL_STAGE(SGL_STAGE_FOLD, launch_fold(p, p.bufX));
   SGL_STAGE(SGL_STAGE_FFT_CH, launch_fft_pass(p, p.passCh, p.bufX, p.bufY, 0, 0, 0));
   SGL_STAGE(SGL_STAGE_FFT_BH, launch_fft_pass(p, p.passBh, p.bufY, p.bufX, 1, 0, 0));
   SGL_STAGE(SGL_STAGE_FFT_AH, launch_fft_pass(p, p.passAh, p.bufX, eta, 2, 2, 0));

@@ -109,13 +109,17 @@ struct Plan {
   void *pts = nullptr;       // PointRec<R>[M], sorted
   int32_t *perm = nullptr;   // sorted position -> caller's index
   int32_t *tile_start = nullptr;  // ntiles + 1
-  int32_t *chunks = nullptr;      // gather work list: {tile, start, count} triples
+  int32_t *chunks = nullptr;      // gather/spread work list: {tile, start, count} triples
   int64_t nchunks = 0;
-  void *krad = nullptr, *kpol = nullptr;  // conversion matrices
+  int32_t *tile_chunk = nullptr;  // ntiles + 1: first chunk of every tile
+  void *staging = nullptr;        // nchunks window boxes (tiled scatter)
+  int F[3] = {8, 8, 8};           // fold block edges (stored cells)
+  void *krad = nullptr, *kpol = nullptr;  // conversion matrices (always FP64)
   void *deconv = nullptr;                 // n0 + n1 + n2 reals
   void *twiddle = nullptr;                // per pass: L complex
   int64_t tw_off[3] = {0, 0, 0};
-  void *beta = nullptr;   // radial output / adjoint input, complex
+  void *beta = nullptr;   // radial output / adjoint input, complex double
+  void *zeta = nullptr;   // polar output in compact form, complex double
   void *eta = nullptr;    // dense eta on the reduced grid, complex
   void *bufX = nullptr;   // FFT scratch T1 and the stored grid G (aliased)
   void *bufY = nullptr;   // FFT scratch T2
@@ -138,6 +142,7 @@ hipError_t launch_fft_pass(const Plan &p, const FftPass &fp, const void *in, voi
                            int deconv_dim_on_input, int deconv_dim_on_output);
 hipError_t launch_gather(const Plan &p, const void *grid, void *f);
 hipError_t launch_scatter(const Plan &p, const void *f, void *grid);
+hipError_t launch_fold(const Plan &p, void *grid);
 hipError_t launch_ndft_forward(const Plan &p, const void *eta, void *f);
 hipError_t launch_ndft_adjoint(const Plan &p, const void *f, void *eta);
 

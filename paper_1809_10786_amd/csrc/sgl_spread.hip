@@ -15,10 +15,15 @@
 //    one point at a time.
 //  * gather (direct): each thread evaluates one point reading the grid
 //    through the cache (used when the window box does not fit in LDS).
-//  * scatter: output-driven; each workgroup owns a block of stored cells,
-//    accumulates the contributions of every point whose taps reach the block
-//    in LDS, and writes the block once.  No global atomics; every cell of the
-//    grid is written by exactly one workgroup.
+//  * scatter (tiled): one workgroup per chunk accumulates all taps of its
+//    points into the tile's window box, held as register rows, and writes the
+//    box to a staging slot of its own; a fold pass then sums, for every stored
+//    cell, the boxes that cover it in a fixed order.  No atomics of any kind:
+//    every grid cell is written by exactly one workgroup.
+//  * scatter (direct): output-driven, for grids whose window box does not fit
+//    in LDS; each workgroup owns a block of stored cells, accumulates in LDS
+//    the contributions of every point whose taps reach the block, and writes
+//    the block once.
 #include "sgl_internal.h"
 
 namespace sgl {
@@ -348,6 +353,181 @@ __global__ __launch_bounds__(256) void k_scatter(const cplx<R> *__restrict__ y, 
   }
 }
 
+// ---------------------------------------------------------------- scatter, tiled
+
+// Spreading for one chunk of points of one tile, without atomics: thread r
+// owns row (i0, i1) of the tile's window box (X2 cells along dimension 2) in
+// registers.  Points are taken in batches: their weights are computed once
+// into LDS -- the dimension-2 weights already shifted to the point's offset
+// in the box and zero elsewhere -- then every thread walks the batch and,
+// when its row lies in the point's footprint, adds c * w2s[i2] to all X2 cells
+// of its row with c = y w0[i0 - o0] w1[i1 - o1].  Every register index is
+// static.  The box is then written to the chunk's own staging slot;
+// k_fold_staging sums overlapping boxes.  The result is independent of
+// scheduling.
+constexpr int kSpreadBatch = 128;
+
+template <class R, int Q2, int L2>
+__global__ __launch_bounds__(512) void k_spread_rows(const cplx<R> *__restrict__ y,
+                                                     const PointRec<R> *__restrict__ pts,
+                                                     const int32_t *__restrict__ perm,
+                                                     const int32_t *__restrict__ chunks, Geom g, R inv2lam,
+                                                     cplx<R> *__restrict__ staging) {
+  constexpr int q = Q2 / 2;
+  constexpr int X2 = L2 + Q2 - 1;
+  constexpr int X2P = (X2 + 3) & ~3;  // row stride of the shifted weights
+  __shared__ R sw0[kSpreadBatch][Q2], sw1[kSpreadBatch][Q2];
+  __shared__ __attribute__((aligned(16))) R sw2[kSpreadBatch][X2P];
+  __shared__ int so[kSpreadBatch];
+  __shared__ cplx<R> sy[kSpreadBatch];
+  const int tidx = chunks[3 * blockIdx.x];
+  const int start = chunks[3 * blockIdx.x + 1];
+  const int count = chunks[3 * blockIdx.x + 2];
+  const int c2 = tidx % g.T[2];
+  const int c1 = (tidx / g.T[2]) % g.T[1];
+  const int c0 = tidx / (g.T[2] * g.T[1]);
+  const int X1 = g.X[1];
+  const int nrow = g.X[0] * X1;
+  const int i0 = threadIdx.x / X1, i1 = threadIdx.x % X1;
+  const bool has_row = (int)threadIdx.x < nrow;
+  R are[X2], aim[X2];
+#pragma unroll
+  for (int i = 0; i < X2; ++i) are[i] = aim[i] = 0;
+  for (int b0 = 0; b0 < count; b0 += kSpreadBatch) {
+    const int nb = min(kSpreadBatch, count - b0);
+    if ((int)threadIdx.x < nb) {
+      const int k = start + b0 + threadIdx.x;
+      const PointRec<R> pr = pts[k];
+      const int o0 = cell0(pr.cell) - c0 * g.L[0];
+      const int o1 = cell1(pr.cell) - c1 * g.L[1];
+      const int o2 = cell2(pr.cell) - c2 * g.L[2];
+      so[threadIdx.x] = o0 | (o1 << 8);
+      sy[threadIdx.x] = y[perm[k]];
+#pragma unroll
+      for (int t = 0; t < Q2; ++t) {
+        sw0[threadIdx.x][t] = gauss<R>(pr.frac[0] + (R)(q - 1 - t), inv2lam);
+        sw1[threadIdx.x][t] = gauss<R>(pr.frac[1] + (R)(q - 1 - t), inv2lam);
+      }
+      for (int c = 0; c < X2P; ++c) {
+        const int t = c - o2;
+        sw2[threadIdx.x][c] = (t >= 0 && t < Q2) ? gauss<R>(pr.frac[2] + (R)(q - 1 - t), inv2lam) : (R)0;
+      }
+    }
+    __syncthreads();
+    if (has_row) {
+      for (int pi = 0; pi < nb; ++pi) {
+        const int o = so[pi];
+        const int t0 = i0 - (o & 255), t1 = i1 - (o >> 8);
+        if ((unsigned)t0 < (unsigned)Q2 && (unsigned)t1 < (unsigned)Q2) {
+          const R w01 = sw0[pi][t0] * sw1[pi][t1];
+          const cplx<R> yv = sy[pi];
+          const R cr = yv.re * w01, ci = yv.im * w01;
+#pragma unroll
+          for (int c = 0; c < X2; ++c) {
+            const R w = sw2[pi][c];
+            are[c] += cr * w;
+            aim[c] += ci * w;
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (has_row) {
+    cplx<R> *out = staging + (size_t)blockIdx.x * nrow * X2 + (size_t)threadIdx.x * X2;
+#pragma unroll
+    for (int i = 0; i < X2; ++i) out[i] = cplx<R>{are[i], aim[i]};
+  }
+}
+
+constexpr int kMaxCand = 256;
+
+// Sum of the staged window boxes into the stored grid: one workgroup per
+// block of F0 x F1 x F2 stored cells; every chunk whose tile's window box
+// overlaps the block is added in a fixed order (tiles, then chunks), so the
+// result does not depend on scheduling.  Each grid cell is written once.
+template <class R>
+__global__ __launch_bounds__(256) void k_fold_staging(const cplx<R> *__restrict__ staging,
+                                                      const int32_t *__restrict__ tile_chunk,
+                                                      Geom g, int F0, int F1, int F2,
+                                                      cplx<R> *__restrict__ grid) {
+  __shared__ int cand[3][kMaxCand];
+  __shared__ int coff[3][kMaxCand];  // region index of the block's first cell
+  __shared__ int ncand[3];
+  const int Tf1 = (g.E[1] + F1 - 1) / F1, Tf2 = (g.E[2] + F2 - 1) / F2;
+  const int C2 = blockIdx.x % Tf2, C1 = (blockIdx.x / Tf2) % Tf1, C0 = blockIdx.x / (Tf2 * Tf1);
+  const int S[3] = {C0 * F0, C1 * F1, C2 * F2};
+  const int F[3] = {F0, F1, F2};
+  const int q = g.q;
+  if (threadIdx.x < 3) {
+    const int j = threadIdx.x;
+    int n = 0;
+    for (int c = 0; c < g.T[j] && n < kMaxCand; ++c) {
+      // stored index of the first cell of tile c's window box
+      const int first = g.pruned[j] ? c * g.L[j] : c * g.L[j] - q + 1;
+      int d = S[j] - first;  // region index of the block start
+      bool hit;
+      if (g.pruned[j]) {
+        hit = d < g.X[j] && d + F[j] > 0;
+      } else {
+        d %= g.N[j];
+        if (d < 0) d += g.N[j];
+        hit = d < g.X[j] || d + F[j] > g.N[j];
+      }
+      if (hit) {
+        cand[j][n] = c;
+        coff[j][n] = d;
+        ++n;
+      }
+    }
+    ncand[j] = n;
+  }
+  __syncthreads();
+  const int ext0 = min(F0, g.E[0] - S[0]), ext1 = min(F1, g.E[1] - S[1]), ext2 = min(F2, g.E[2] - S[2]);
+  const int ncell = g.X[0] * g.X[1] * g.X[2];
+  // Region index of block cell u in a box whose block-start index is d: d + u,
+  // modulo N in the periodic dimension (where a box longer than the period
+  // holds the same cell more than once, every copy counts).
+  const int step0 = g.pruned[0] ? (1 << 30) : g.N[0];
+  const int step1 = g.pruned[1] ? (1 << 30) : g.N[1];
+  const int step2 = g.pruned[2] ? (1 << 30) : g.N[2];
+  for (int e = threadIdx.x; e < ext0 * ext1 * ext2; e += blockDim.x) {
+    const int u2 = e % ext2, r = e / ext2, u1 = r % ext1, u0 = r / ext1;
+    R ar = 0, ai = 0;
+    for (int a = 0; a < ncand[0]; ++a) {
+      int j0 = coff[0][a] + u0;
+      if (!g.pruned[0] && j0 >= g.N[0]) j0 -= g.N[0];
+      for (int i0 = j0; i0 < g.X[0]; i0 += step0) {
+        if (i0 < 0) continue;
+        for (int b = 0; b < ncand[1]; ++b) {
+          int j1 = coff[1][b] + u1;
+          if (!g.pruned[1] && j1 >= g.N[1]) j1 -= g.N[1];
+          for (int i1 = j1; i1 < g.X[1]; i1 += step1) {
+            if (i1 < 0) continue;
+            for (int c = 0; c < ncand[2]; ++c) {
+              const int tile = (cand[0][a] * g.T[1] + cand[1][b]) * g.T[2] + cand[2][c];
+              const int ch0 = tile_chunk[tile], ch1 = tile_chunk[tile + 1];
+              if (ch0 == ch1) continue;
+              int j2 = coff[2][c] + u2;
+              if (!g.pruned[2] && j2 >= g.N[2]) j2 -= g.N[2];
+              for (int i2 = j2; i2 < g.X[2]; i2 += step2) {
+                if (i2 < 0) continue;
+                const size_t off = ((size_t)i0 * g.X[1] + i1) * g.X[2] + i2;
+                for (int ch = ch0; ch < ch1; ++ch) {
+                  const cplx<R> v = staging[(size_t)ch * ncell + off];
+                  ar += v.re;
+                  ai += v.im;
+                }
+              }
+            }
+          }
+        }
+      }
+    }
+    grid[((size_t)(S[0] + u0) * g.E[1] + (S[1] + u1)) * g.E[2] + (S[2] + u2)] = cplx<R>{ar, ai};
+  }
+}
+
 // ---------------------------------------------------------------- exact NDFT
 
 // p(t_i) = sum_{k in I_n} eta_k e^{i <k, t_i>}, directly (Def. 2.4).
@@ -438,9 +618,33 @@ template <class R, int Q2>
 hipError_t scatter_q(const Plan &p, const void *f, void *grid) {
   const Geom g = make_geom(p);
   const R inv2lam = (R)(1.0 / (2.0 * p.lambda));
+  if (p.gather_mode == 0) {
+    if constexpr (Q2 <= 16) {
+      const unsigned threads = (unsigned)((p.X[0] * p.X[1] + 63) / 64 * 64);
+      if (p.L[2] == 8)
+        k_spread_rows<R, Q2, 8><<<(unsigned)p.nchunks, threads, 0, p.stream>>>(
+            (const cplx<R> *)f, (const PointRec<R> *)p.pts, p.perm, p.chunks, g, inv2lam, (cplx<R> *)p.staging);
+      else
+        k_spread_rows<R, Q2, 4><<<(unsigned)p.nchunks, threads, 0, p.stream>>>(
+            (const cplx<R> *)f, (const PointRec<R> *)p.pts, p.perm, p.chunks, g, inv2lam, (cplx<R> *)p.staging);
+      return hipGetLastError();
+    } else {
+      return hipErrorInvalidValue;
+    }
+  }
   const size_t lds = 2 * (size_t)p.Lo[0] * p.Lo[1] * p.Lo[2] * sizeof(R);
   k_scatter<R, Q2><<<(unsigned)p.nblocks, 256, lds, p.stream>>>((const cplx<R> *)f, (const PointRec<R> *)p.pts,
                                                                 p.perm, p.tile_start, g, inv2lam, (cplx<R> *)grid);
+  return hipGetLastError();
+}
+
+template <class R>
+hipError_t fold_r(const Plan &p, void *grid) {
+  const Geom g = make_geom(p);
+  const int F0 = p.F[0], F1 = p.F[1], F2 = p.F[2];
+  const int64_t nb = (int64_t)((p.E[0] + F0 - 1) / F0) * ((p.E[1] + F1 - 1) / F1) * ((p.E[2] + F2 - 1) / F2);
+  k_fold_staging<R><<<(unsigned)nb, 256, 0, p.stream>>>((const cplx<R> *)p.staging, p.tile_chunk, g, F0, F1, F2,
+                                                        (cplx<R> *)grid);
   return hipGetLastError();
 }
 
@@ -481,6 +685,10 @@ hipError_t launch_scatter(const Plan &p, const void *f, void *grid) {
   } else {
     SGL_Q_CASES(scatter_q, float, p, f, grid)
   }
+}
+
+hipError_t launch_fold(const Plan &p, void *grid) {
+  return p.prec == SGL_F64 ? fold_r<double>(p, grid) : fold_r<float>(p, grid);
 }
 
 hipError_t launch_ndft_forward(const Plan &p, const void *eta, void *f) {

@@ -54,25 +54,28 @@ void build_radial_table(int B, double rho, std::vector<long double> &out, std::v
   out.assign(off[B], 0.0L);
   std::vector<long double> lag(B);
   std::vector<long double> rad((size_t)2 * B * B);  // rad[j][k] for the current l
+  std::vector<long double> ctab((size_t)4 * B * B);  // cos(a w_j)
+  for (int a = 0; a < 2 * B; ++a)
+    for (int j = 0; j < 2 * B; ++j) ctab[(size_t)a * 2 * B + j] = cosl(a * node(B, j));
   for (int l = 0; l < B; ++l) {
     const int K = B - l;
     const long double alpha = l + 0.5L;
+    // N_nl = sqrt(2 (n-l-1)! / Gamma(n + 1/2))   (Def. 1.1), n = l + 1 + k
+    std::vector<long double> Nn(K);
+    for (int k = 0; k < K; ++k) Nn[k] = sqrtl(2.0L * expl(lgammal(k + 1.0L) - lgammal(l + 1 + k + 0.5L)));
     for (int j = 0; j < 2 * B; ++j) {
       const long double r = (long double)rho * (1.0L + cosl(node(B, j))) / 2.0L;
       laguerre(K, alpha, r * r, lag.data());
       const long double rl = powl(r, (long double)l);
       for (int k = 0; k < K; ++k) {
-        const int n = l + 1 + k;
-        // N_nl = sqrt(2 (n-l-1)! / Gamma(n + 1/2))   (Def. 1.1)
-        const long double Nnl = sqrtl(2.0L * expl(lgammal(k + 1.0L) - lgammal(n + 0.5L)));
-        rad[(size_t)j * K + k] = Nnl * lag[k] * rl;
+        rad[(size_t)j * K + k] = Nn[k] * lag[k] * rl;
       }
     }
     long double *Kl = out.data() + off[l];
     for (int a = 0; a < 2 * B - 1; ++a)
       for (int k = 0; k < K; ++k) {
         long double s = 0.0L;
-        for (int j = 0; j < 2 * B; ++j) s += cosl(a * node(B, j)) * rad[(size_t)j * K + k];
+        for (int j = 0; j < 2 * B; ++j) s += ctab[(size_t)a * 2 * B + j] * rad[(size_t)j * K + k];
         Kl[(size_t)a * K + k] = s / (2.0L * B);
       }
   }
@@ -101,17 +104,21 @@ void build_polar_table(int B, std::vector<long double> &out, std::vector<int64_t
   for (int m = 0; m < B; ++m) off[m + 1] = off[m] + (int64_t)B * (B - m);
   out.assign(off[B], 0.0L);
   std::vector<long double> leg((size_t)2 * B * B);
+  std::vector<long double> ctab((size_t)2 * B * B), stab((size_t)2 * B * B);  // cos, sin(k1 w_j)
+  for (int k1 = 0; k1 < B; ++k1)
+    for (int j = 0; j < 2 * B; ++j) {
+      ctab[(size_t)k1 * 2 * B + j] = cosl(k1 * node(B, j));
+      stab[(size_t)k1 * 2 * B + j] = sinl(k1 * node(B, j));
+    }
   for (int m = 0; m < B; ++m) {
     const int K = B - m;
     for (int j = 0; j < 2 * B; ++j) legendre_normalised(B, m, cosl(node(B, j)), leg.data() + (size_t)j * K);
     long double *Km = out.data() + off[m];
     for (int k1 = 0; k1 < B; ++k1)
       for (int c = 0; c < K; ++c) {
+        const long double *tr = ((m & 1) ? stab.data() : ctab.data()) + (size_t)k1 * 2 * B;
         long double s = 0.0L;
-        for (int j = 0; j < 2 * B; ++j) {
-          const long double w = node(B, j);
-          s += ((m & 1) ? sinl(k1 * w) : cosl(k1 * w)) * leg[(size_t)j * K + c];
-        }
+        for (int j = 0; j < 2 * B; ++j) s += tr[j] * leg[(size_t)j * K + c];
         Km[(size_t)k1 * K + c] = s / (2.0L * B);
       }
   }

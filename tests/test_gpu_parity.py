@@ -45,7 +45,7 @@ def dev(x, dtype):
 
 def plan(pts, B, prec="f64", q=6, **kw):
     rdt = torch.float64 if prec == "f64" else torch.float32
-    return _sgl().Plan(dev(pts, rdt), B, q=q, precision=prec, **kw)
+    return _sgl().Plan(dev(pts, rdt), B, q=min(q, 2 * B), precision=prec, **kw)
 
 
 def cdt(prec):
@@ -109,11 +109,15 @@ def test_conversion_stage_matches_stepwise(B):
     assert rel(g, g0) < 1e-12
 
 
-@pytest.mark.parametrize("B,q", [(4, 3), (8, 6), (8, 16), (12, 5)])
+@pytest.mark.parametrize("B,q", [(4, 3), (8, 6), (8, 16), (12, 5), (10, 4), (24, 5)])
 def test_nfft_stage_matches_stepwise(B, q):
+    """rho = 1.1 max|x|: near r = rho, t0 = arccos(gamma(r)) grows like sqrt(rho - r),
+    so a one-ulp difference in r between numpy and the device moves t0 by ~1e-8;
+    with a random eta (not even in k0) that alone shows up as ~1e-8 relative.
+    The transform itself is even in t0 and does not see it."""
     say(f"nfft stage B={B} q={q}")
     pts = wl.gaussian_points(700, 20 + B)
-    p = plan(pts, B, q=q)
+    p = plan(pts, B, q=q, rho=1.1 * np.linalg.norm(pts, axis=1).max())
     rng = np.random.default_rng(30 + B)
     eta = (rng.standard_normal(p.eta_shape) + 1j * rng.standard_normal(p.eta_shape))
     f = host(p.nfft_forward(dev(eta, torch.complex128)))
