@@ -47,9 +47,11 @@ bool radices_of(int L, FftPass &fp) {
   return r == 1;
 }
 
+// Lines per FFT workgroup: two LDS buffers of L x W elements plus the L
+// twiddles must fit the LDS budget.
 int lines_per_group(int L, size_t elem) {
   int W = 1;
-  while (W < 32 && 2 * (size_t)L * (W * 2) * elem <= kLdsBudget) W *= 2;
+  while (W < 32 && (2 * (size_t)L * (W * 2) + L) * elem <= kLdsBudget) W *= 2;
   return W;
 }
 
@@ -80,21 +82,20 @@ hipError_t upload_real(Plan &p, void **dst, const std::vector<long double> &v) {
   return hipMemcpy(*dst, h.data(), h.size() * sizeof(R), hipMemcpyHostToDevice);
 }
 
-template <class R>
 hipError_t upload_twiddles(Plan &p) {
-  std::vector<R> h;
+  std::vector<double> h;
   for (int j = 0; j < 3; ++j) {
     std::vector<long double> re, im;
     build_twiddles(p.N[j], +1, re, im);
     p.tw_off[j] = (int64_t)h.size() / 2;
     for (int t = 0; t < p.N[j]; ++t) {
-      h.push_back((R)re[t]);
-      h.push_back((R)im[t]);
+      h.push_back((double)re[t]);
+      h.push_back((double)im[t]);
     }
   }
-  hipError_t e = dev_alloc(p, &p.twiddle, h.size() * sizeof(R));
+  hipError_t e = dev_alloc(p, &p.twiddle, h.size() * sizeof(double));
   if (e != hipSuccess) return e;
-  return hipMemcpy(p.twiddle, h.data(), h.size() * sizeof(R), hipMemcpyHostToDevice);
+  return hipMemcpy(p.twiddle, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice);
 }
 
 bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
@@ -166,6 +167,7 @@ sgl_status setup_geometry(Plan &p) {
   }
   if (rows > 512) return SGL_E_UNSUPPORTED;
   // FFT passes: [outer][axis][inner] views
+  // forward passes run in the plan's precision, adjoint passes in FP64
   auto pass = [&](FftPass &fp, int j, int outer, int inner, int nin, int in_off, int nout, int out_off, int sign) {
     radices_of(p.N[j], fp);
     fp.outer = outer;
@@ -175,7 +177,7 @@ sgl_status setup_geometry(Plan &p) {
     fp.nout = nout;
     fp.out_off = out_off;
     fp.sign = sign;
-    fp.W = lines_per_group(p.N[j], cb);
+    fp.W = lines_per_group(p.N[j], sign > 0 ? cb : 16);
   };
   const int n0 = p.n[0], n1 = p.n[1], n2 = p.n[2];
   pass(p.passA, 2, n0 * n1, 1, n2, -n2 / 2, p.N[2], 0, +1);
@@ -195,8 +197,8 @@ sgl_status build_tables(Plan &p) {
   build_deconv(p, dc);
   SGL_TRY(upload_real<double>(p, &p.krad, kr));
   SGL_TRY(upload_real<double>(p, &p.kpol, kp));
-  SGL_TRY(upload_real<R>(p, &p.deconv, dc));
-  SGL_TRY(upload_twiddles<R>(p));
+  SGL_TRY(upload_real<double>(p, &p.deconv, dc));
+  SGL_TRY(upload_twiddles(p));
   return SGL_OK;
 }
 
@@ -278,9 +280,10 @@ sgl_status make_plan(Plan &p, const void *points) {
   const size_t nG = (size_t)p.E[0] * p.E[1] * p.E[2];
   SGL_TRY(dev_alloc(p, &p.beta, nbeta * 16));
   SGL_TRY(dev_alloc(p, &p.zeta, (size_t)(2 * B - 1) * B * (2 * B - 1) * 16));  // compact zeta
-  SGL_TRY(dev_alloc(p, &p.eta, neta * cb));
-  SGL_TRY(dev_alloc(p, &p.bufX, std::max(nT1, nG) * cb));
-  SGL_TRY(dev_alloc(p, &p.bufY, nT2 * cb));
+  // eta and the FFT scratch hold double values on the adjoint side in both precisions
+  SGL_TRY(dev_alloc(p, &p.eta, neta * 16));
+  SGL_TRY(dev_alloc(p, &p.bufX, std::max(nT1, nG) * 16));
+  SGL_TRY(dev_alloc(p, &p.bufY, nT2 * 16));
   SGL_TRY(hipStreamSynchronize(p.stream));
   return SGL_OK;
 }
@@ -328,8 +331,8 @@ sgl_status conv_fwd(Plan &p, const void *fhat, void *eta) {
   return SGL_OK;
 }
 
-sgl_status conv_adj(Plan &p, const void *eta, void *fhat) {
-  SGL_STAGE(SGL_STAGE_CONV_POLAR_ADJ, launch_conv_polar_adj(p, eta));
+sgl_status conv_adj(Plan &p, const void *eta, int eta_f64, void *fhat) {
+  SGL_STAGE(SGL_STAGE_CONV_POLAR_ADJ, launch_conv_polar_adj(p, eta, eta_f64));
   SGL_STAGE(SGL_STAGE_CONV_RADIAL_ADJ, launch_conv_radial_adj(p, fhat));
   return SGL_OK;
 }
@@ -339,23 +342,28 @@ sgl_status nfft_fwd(Plan &p, const void *eta, void *f) {
     SGL_STAGE(SGL_STAGE_NDFT, launch_ndft_forward(p, eta, f));
     return SGL_OK;
   }
-  SGL_STAGE(SGL_STAGE_FFT_A, launch_fft_pass(p, p.passA, eta, p.bufX, 2, 1, 0));
-  SGL_STAGE(SGL_STAGE_FFT_B, launch_fft_pass(p, p.passB, p.bufX, p.bufY, 1, 0, 0));
-  SGL_STAGE(SGL_STAGE_FFT_C, launch_fft_pass(p, p.passC, p.bufY, p.bufX, 0, 0, 0));
+  const int f64 = p.prec == SGL_F64;
+  SGL_STAGE(SGL_STAGE_FFT_A, launch_fft_pass(p, p.passA, eta, p.bufX, 2, 1, f64, f64));
+  SGL_STAGE(SGL_STAGE_FFT_B, launch_fft_pass(p, p.passB, p.bufX, p.bufY, 1, 0, f64, f64));
+  SGL_STAGE(SGL_STAGE_FFT_C, launch_fft_pass(p, p.passC, p.bufY, p.bufX, 0, 0, f64, f64));
   SGL_STAGE(SGL_STAGE_GATHER, launch_gather(p, p.bufX, f));
   return SGL_OK;
 }
 
-sgl_status nfft_adj(Plan &p, const void *f, void *eta) {
+// eta_f64: element type of the eta output (the adjoint FFT itself runs in FP64).
+sgl_status nfft_adj(Plan &p, const void *f, void *eta, int eta_f64) {
   if (p.flags & SGL_FLAG_EXACT_NDFT) {
+    if (eta_f64 != (p.prec == SGL_F64)) return SGL_E_INVAL;
     SGL_STAGE(SGL_STAGE_NDFT_ADJ, launch_ndft_adjoint(p, f, eta));
     return SGL_OK;
   }
   SGL_STAGE(SGL_STAGE_SCATTER, launch_scatter(p, f, p.bufX));
   if (p.gather_mode == 0) SGL_STAGE(SGL_STAGE_FOLD, launch_fold(p, p.bufX));
-  SGL_STAGE(SGL_STAGE_FFT_CH, launch_fft_pass(p, p.passCh, p.bufX, p.bufY, 0, 0, 0));
-  SGL_STAGE(SGL_STAGE_FFT_BH, launch_fft_pass(p, p.passBh, p.bufY, p.bufX, 1, 0, 0));
-  SGL_STAGE(SGL_STAGE_FFT_AH, launch_fft_pass(p, p.passAh, p.bufX, eta, 2, 2, 0));
+  // the folded grid is double; the direct scatter writes the plan's precision
+  const int grid_f64 = (p.gather_mode == 0 || p.prec == SGL_F64) ? 1 : 0;
+  SGL_STAGE(SGL_STAGE_FFT_CH, launch_fft_pass(p, p.passCh, p.bufX, p.bufY, 0, 0, grid_f64, 1));
+  SGL_STAGE(SGL_STAGE_FFT_BH, launch_fft_pass(p, p.passBh, p.bufY, p.bufX, 1, 0, 1, 1));
+  SGL_STAGE(SGL_STAGE_FFT_AH, launch_fft_pass(p, p.passAh, p.bufX, eta, 2, 2, 1, eta_f64));
   return SGL_OK;
 }
 
@@ -442,7 +450,7 @@ sgl_status sgl_conv_adjoint(sgl_plan_t plan, const void *eta_dev, void *fhat_dev
   Plan &p = plan->p;
   const size_t cb = cbytes(p);
   if (overlaps(fhat_dev, sgl_num_coeffs(p.B) * cb, eta_dev, (size_t)p.n[0] * p.n[1] * p.n[2] * cb)) return SGL_E_INVAL;
-  return conv_adj(p, eta_dev, fhat_dev);
+  return conv_adj(p, eta_dev, p.prec == SGL_F64, fhat_dev);
 }
 
 sgl_status sgl_nfft_forward(sgl_plan_t plan, const void *eta_dev, void *f_dev) {
@@ -458,7 +466,7 @@ sgl_status sgl_nfft_adjoint(sgl_plan_t plan, const void *f_dev, void *eta_dev) {
   Plan &p = plan->p;
   const size_t cb = cbytes(p);
   if (overlaps(eta_dev, (size_t)p.n[0] * p.n[1] * p.n[2] * cb, f_dev, (size_t)p.M * cb)) return SGL_E_INVAL;
-  return nfft_adj(p, f_dev, eta_dev);
+  return nfft_adj(p, f_dev, eta_dev, p.prec == SGL_F64);
 }
 
 sgl_status sgl_forward(sgl_plan_t plan, const void *fhat_dev, void *f_dev) {
@@ -476,9 +484,11 @@ sgl_status sgl_adjoint(sgl_plan_t plan, const void *f_dev, void *fhat_dev) {
   Plan &p = plan->p;
   const size_t cb = cbytes(p);
   if (overlaps(fhat_dev, sgl_num_coeffs(p.B) * cb, f_dev, (size_t)p.M * cb)) return SGL_E_INVAL;
-  const sgl_status st = nfft_adj(p, f_dev, p.eta);
+  const int exact = (p.flags & SGL_FLAG_EXACT_NDFT) != 0;
+  const int eta_f64 = exact ? (p.prec == SGL_F64) : 1;  // NFFT adjoint hands FP64 eta to the conversion
+  const sgl_status st = nfft_adj(p, f_dev, p.eta, eta_f64);
   if (st != SGL_OK) return st;
-  return conv_adj(p, p.eta, fhat_dev);
+  return conv_adj(p, p.eta, eta_f64, fhat_dev);
 }
 
 sgl_status sgl_plan_rho(sgl_plan_t plan, double *rho) {

@@ -232,7 +232,7 @@ hipError_t polar(const Plan &p, void *eta) {
 }
 
 template <class R>
-hipError_t polar_adj(const Plan &p, const void *eta) {
+hipError_t polar_adj(const Plan &p, const void *eta) {  // R: element type of eta
   const int B = p.B, A = 2 * B - 1;
   k_fold_eta<R><<<nblk((int64_t)A * B * A), 256, 0, p.stream>>>(B, (const cplx<R> *)eta, (cplx<double> *)p.zeta);
   k_polar_adj<<<nblk((int64_t)A * B * A), 256, 0, p.stream>>>(B, (const double *)p.kpol,
@@ -256,8 +256,8 @@ hipError_t launch_conv_radial(const Plan &p, const void *fhat) {
 hipError_t launch_conv_polar(const Plan &p, void *eta) {
   return p.prec == SGL_F64 ? polar<double>(p, eta) : polar<float>(p, eta);
 }
-hipError_t launch_conv_polar_adj(const Plan &p, const void *eta) {
-  return p.prec == SGL_F64 ? polar_adj<double>(p, eta) : polar_adj<float>(p, eta);
+hipError_t launch_conv_polar_adj(const Plan &p, const void *eta, int eta_f64) {
+  return eta_f64 ? polar_adj<double>(p, eta) : polar_adj<float>(p, eta);
 }
 hipError_t launch_conv_radial_adj(const Plan &p, void *fhat) {
   return p.prec == SGL_F64 ? radial_adj<double>(p, fhat) : radial_adj<float>(p, fhat);

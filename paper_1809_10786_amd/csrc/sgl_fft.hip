@@ -135,14 +135,17 @@ __device__ inline int wrap(int i, int L) {
 
 // dcmode: 0 none; 1 multiply input row i of line o by dc0[o / n1] dc1[o % n1]
 // dc2[i]; 2 the same on output rows (pass A of the forward / adjoint).
-template <class R>
-__global__ __launch_bounds__(256) void k_fft(const cplx<R> *__restrict__ in, cplx<R> *__restrict__ out, FftPass fp,
-                                             const cplx<R> *__restrict__ tw, const R *__restrict__ dc, int dcmode,
-                                             int n0, int n1) {
+// Ri: element type read, R: type of the transform and of the output.
+template <class Ri, class R>
+__global__ __launch_bounds__(256) void k_fft(const cplx<Ri> *__restrict__ in, cplx<R> *__restrict__ out, FftPass fp,
+                                             const cplx<double> *__restrict__ tw64, const double *__restrict__ dc,
+                                             int dcmode, int n0, int n1) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int L = fp.L, W = fp.W;
   cplx<R> *buf0 = (cplx<R> *)smem;
   cplx<R> *buf1 = buf0 + (size_t)L * W;
+  cplx<R> *tw = buf1 + (size_t)L * W;  // twiddles e^{2 pi i t / L} in the transform's precision
+  for (int t = threadIdx.x; t < L; t += blockDim.x) tw[t] = cplx<R>{(R)tw64[t].re, (R)tw64[t].im};
 
   // line w of this workgroup -> (outer index o, inner index ic)
   int o_base, ic_base;
@@ -170,8 +173,9 @@ __global__ __launch_bounds__(256) void k_fft(const cplx<R> *__restrict__ in, cpl
     const int o = fp.inner > 1 ? o_base : o_base + w;
     const int ic = fp.inner > 1 ? ic_base + w : 0;
     if (o >= fp.outer || ic >= fp.inner) continue;
-    cplx<R> v = in[((size_t)o * fp.nin + i) * fp.inner + ic];
-    if (dcmode == 1) v = cscale(v, dc[o / n1] * dc[n0 + o % n1] * dc[n0 + n1 + i]);
+    const cplx<Ri> vi = in[((size_t)o * fp.nin + i) * fp.inner + ic];
+    cplx<R> v = {(R)vi.re, (R)vi.im};
+    if (dcmode == 1) v = cscale(v, (R)(dc[o / n1] * dc[n0 + o % n1] * dc[n0 + n1 + i]));
     buf0[wrap(fp.in_off + i, L) * W + w] = v;
   }
   __syncthreads();
@@ -207,28 +211,29 @@ __global__ __launch_bounds__(256) void k_fft(const cplx<R> *__restrict__ in, cpl
     const int ic = fp.inner > 1 ? ic_base + w : 0;
     if (o >= fp.outer || ic >= fp.inner) continue;
     cplx<R> v = src[wrap(fp.out_off + i, L) * W + w];
-    if (dcmode == 2) v = cscale(v, dc[o / n1] * dc[n0 + o % n1] * dc[n0 + n1 + i]);
+    if (dcmode == 2) v = cscale(v, (R)(dc[o / n1] * dc[n0 + o % n1] * dc[n0 + n1 + i]));
     out[((size_t)o * fp.nout + i) * fp.inner + ic] = v;
   }
 }
 
 }  // namespace
 
-hipError_t launch_fft_pass(const Plan &p, const FftPass &fp, const void *in, void *out, int tw_index, int dcmode,
-                           int /*unused*/) {
+template <class Ri, class R>
+hipError_t fft_typed(const Plan &p, const FftPass &fp, const void *in, void *out, int tw_index, int dcmode) {
   const int groups = fp.inner > 1 ? fp.outer * ((fp.inner + fp.W - 1) / fp.W) : (fp.outer + fp.W - 1) / fp.W;
-  if (p.prec == SGL_F64) {
-    const size_t lds = 2 * (size_t)fp.L * fp.W * sizeof(cplx<double>);
-    k_fft<double><<<groups, 256, lds, p.stream>>>((const cplx<double> *)in, (cplx<double> *)out, fp,
-                                                  (const cplx<double> *)p.twiddle + p.tw_off[tw_index],
-                                                  (const double *)p.deconv, dcmode, p.n[0], p.n[1]);
-  } else {
-    const size_t lds = 2 * (size_t)fp.L * fp.W * sizeof(cplx<float>);
-    k_fft<float><<<groups, 256, lds, p.stream>>>((const cplx<float> *)in, (cplx<float> *)out, fp,
-                                                 (const cplx<float> *)p.twiddle + p.tw_off[tw_index],
-                                                 (const float *)p.deconv, dcmode, p.n[0], p.n[1]);
-  }
+  const size_t lds = (2 * (size_t)fp.L * fp.W + fp.L) * sizeof(cplx<R>);
+  k_fft<Ri, R><<<groups, 256, lds, p.stream>>>((const cplx<Ri> *)in, (cplx<R> *)out, fp,
+                                               (const cplx<double> *)p.twiddle + p.tw_off[tw_index],
+                                               (const double *)p.deconv, dcmode, p.n[0], p.n[1]);
   return hipGetLastError();
+}
+
+hipError_t launch_fft_pass(const Plan &p, const FftPass &fp, const void *in, void *out, int tw_index, int dcmode,
+                           int in_f64, int out_f64) {
+  if (in_f64 && out_f64) return fft_typed<double, double>(p, fp, in, out, tw_index, dcmode);
+  if (!in_f64 && out_f64) return fft_typed<float, double>(p, fp, in, out, tw_index, dcmode);
+  if (in_f64 && !out_f64) return fft_typed<double, float>(p, fp, in, out, tw_index, dcmode);
+  return fft_typed<float, float>(p, fp, in, out, tw_index, dcmode);
 }
 
 }  // namespace sgl

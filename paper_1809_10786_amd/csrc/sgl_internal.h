@@ -116,11 +116,11 @@ struct Plan {
   int F[3] = {8, 8, 8};           // fold block edges (stored cells)
   void *krad = nullptr, *kpol = nullptr;  // conversion matrices (always FP64)
   void *deconv = nullptr;                 // n0 + n1 + n2 reals
-  void *twiddle = nullptr;                // per pass: L complex
+  void *twiddle = nullptr;                // per dimension: N_j complex double
   int64_t tw_off[3] = {0, 0, 0};
   void *beta = nullptr;   // radial output / adjoint input, complex double
   void *zeta = nullptr;   // polar output in compact form, complex double
-  void *eta = nullptr;    // dense eta on the reduced grid, complex
+  void *eta = nullptr;    // dense eta on the reduced grid (complex double in both precisions)
   void *bufX = nullptr;   // FFT scratch T1 and the stored grid G (aliased)
   void *bufY = nullptr;   // FFT scratch T2
   void *ptsxyz = nullptr; // for the exact NDFT: transformed points t (double, 3 x M)
@@ -136,13 +136,15 @@ hipError_t launch_point_prep(Plan &p, const void *xyz, uint32_t *keys, int32_t *
 hipError_t launch_point_sort(Plan &p, uint32_t *keys, int32_t *idx, void *unsorted);
 hipError_t launch_conv_radial(const Plan &p, const void *fhat);
 hipError_t launch_conv_polar(const Plan &p, void *eta);
-hipError_t launch_conv_polar_adj(const Plan &p, const void *eta);
+hipError_t launch_conv_polar_adj(const Plan &p, const void *eta, int eta_f64);
 hipError_t launch_conv_radial_adj(const Plan &p, void *fhat);
-hipError_t launch_fft_pass(const Plan &p, const FftPass &fp, const void *in, void *out, int tw_index,
-                           int deconv_dim_on_input, int deconv_dim_on_output);
+// One FFT pass; in_f64/out_f64 select double or float elements (float input
+// with double output widens; the transform runs in the output precision).
+hipError_t launch_fft_pass(const Plan &p, const FftPass &fp, const void *in, void *out, int tw_index, int dcmode,
+                           int in_f64, int out_f64);
 hipError_t launch_gather(const Plan &p, const void *grid, void *f);
 hipError_t launch_scatter(const Plan &p, const void *f, void *grid);
-hipError_t launch_fold(const Plan &p, void *grid);
+hipError_t launch_fold(const Plan &p, void *grid);  // writes a double grid in both precisions
 hipError_t launch_ndft_forward(const Plan &p, const void *eta, void *f);
 hipError_t launch_ndft_adjoint(const Plan &p, const void *f, void *eta);
 

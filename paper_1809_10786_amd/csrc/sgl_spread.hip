@@ -445,12 +445,16 @@ constexpr int kMaxCand = 256;
 // Sum of the staged window boxes into the stored grid: one workgroup per
 // block of F0 x F1 x F2 stored cells; every chunk whose tile's window box
 // overlaps the block is added in a fixed order (tiles, then chunks), so the
-// result does not depend on scheduling.  Each grid cell is written once.
+// result does not depend on scheduling.  Each grid cell is written once, in
+// double precision: the adjoint FFT and the adjoint conversion that follow
+// amplify relative errors of the grid (the conversion tables grow with the
+// radial functions towards r = rho), so the FP32 mode keeps its boxes in
+// FP32 but sums and transforms them in FP64.
 template <class R>
 __global__ __launch_bounds__(256) void k_fold_staging(const cplx<R> *__restrict__ staging,
                                                       const int32_t *__restrict__ tile_chunk,
                                                       Geom g, int F0, int F1, int F2,
-                                                      cplx<R> *__restrict__ grid) {
+                                                      cplx<double> *__restrict__ grid) {
   __shared__ int cand[3][kMaxCand];
   __shared__ int coff[3][kMaxCand];  // region index of the block's first cell
   __shared__ int ncand[3];
@@ -493,7 +497,7 @@ __global__ __launch_bounds__(256) void k_fold_staging(const cplx<R> *__restrict_
   const int step2 = g.pruned[2] ? (1 << 30) : g.N[2];
   for (int e = threadIdx.x; e < ext0 * ext1 * ext2; e += blockDim.x) {
     const int u2 = e % ext2, r = e / ext2, u1 = r % ext1, u0 = r / ext1;
-    R ar = 0, ai = 0;
+    double ar = 0, ai = 0;
     for (int a = 0; a < ncand[0]; ++a) {
       int j0 = coff[0][a] + u0;
       if (!g.pruned[0] && j0 >= g.N[0]) j0 -= g.N[0];
@@ -524,7 +528,7 @@ __global__ __launch_bounds__(256) void k_fold_staging(const cplx<R> *__restrict_
         }
       }
     }
-    grid[((size_t)(S[0] + u0) * g.E[1] + (S[1] + u1)) * g.E[2] + (S[2] + u2)] = cplx<R>{ar, ai};
+    grid[((size_t)(S[0] + u0) * g.E[1] + (S[1] + u1)) * g.E[2] + (S[2] + u2)] = cplx<double>{ar, ai};
   }
 }
 
@@ -644,7 +648,7 @@ hipError_t fold_r(const Plan &p, void *grid) {
   const int F0 = p.F[0], F1 = p.F[1], F2 = p.F[2];
   const int64_t nb = (int64_t)((p.E[0] + F0 - 1) / F0) * ((p.E[1] + F1 - 1) / F1) * ((p.E[2] + F2 - 1) / F2);
   k_fold_staging<R><<<(unsigned)nb, 256, 0, p.stream>>>((const cplx<R> *)p.staging, p.tile_chunk, g, F0, F1, F2,
-                                                        (cplx<R> *)grid);
+                                                        (cplx<double> *)grid);
   return hipGetLastError();
 }
 
