@@ -39,7 +39,16 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--check-points", type=int, default=2000)
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="MiB copied by a plain device copy before the timed region (counter calibration)")
+    ap.add_argument("--summarize", nargs=3, metavar=("KT_DIR", "FETCH_DIR", "WRITE_DIR"),
+                    help="summarize rocprofv3 output directories into --summary-out and exit")
+    ap.add_argument("--summary-out", default=os.path.join(ROOT, "profiles", "nfsglft_b64_m4e6_f32.md"))
     return ap.parse_args()
+
+
+PROFILE_COMMAND = ("rocprofv3 {mode} -T -f csv -d gpurun_out/prof_{tag} -o {tag} -- python3 bench.py --steps {steps} "
+                   "--warmup 1 --no-cpu-baseline --check-points 0 --copy-calibration 256")
 
 
 def spread_flops(q):
@@ -103,8 +112,92 @@ def accuracy(B, plan, pts_used, fh_used, f_gpu, y, prec, m, torch, cdt):
             "adj_rel_linf": ni(g, g0), "sample_points": m}
 
 
+# ---------------------------------------------------------------- profiles
+
+STAGE_KERNEL = {"gather": "k_gather_tiled", "scatter": "k_spread_rows", "fold": "k_fold_staging"}
+KERNEL_SOURCE = {"k_gather_tiled": "sgl_spread.hip", "k_spread_rows": "sgl_spread.hip",
+                 "k_fold_staging": "sgl_spread.hip", "k_fft": "sgl_fft.hip"}
+
+
+def source_digest(kernel):
+    import hashlib
+
+    path = os.path.join(ROOT, "paper_1809_10786_amd", "csrc", KERNEL_SOURCE.get(kernel, "sgl_spread.hip"))
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def summarize_profiles(kt_dir, fetch_dir, write_dir, out_md, command):
+    """Write a markdown summary of one rocprofv3 kernel-trace/stats run and two
+    counter runs (FETCH_SIZE, WRITE_SIZE) of this script.  The counters are
+    scaled by what they read for the plain 256 MiB device copy that the
+    profiled command performs (--copy-calibration 256)."""
+    import csv
+    import glob
+
+    def one(pattern):
+        return glob.glob(os.path.join(pattern))[0]
+
+    stats = list(csv.DictReader(open(one(os.path.join(kt_dir, "*_kernel_stats.csv")))))
+    counters = {}
+    for d, name in ((fetch_dir, "FETCH_SIZE"), (write_dir, "WRITE_SIZE")):
+        rows = list(csv.DictReader(open(one(os.path.join(d, "*_counter_collection.csv")))))
+        calib = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]]
+        calib = max(calib) if calib else 0.0
+        factor = (256 * 1024) / calib if calib else 1.0
+        per = {}
+        for r in rows:
+            per.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]) * factor * 1024)
+        counters[name] = (factor, {k: sum(v) / len(v) for k, v in per.items()})
+    lines = [f"# rocprofv3 summary: {os.path.basename(out_md)[:-3]}", "",
+             "Command (kernel trace and statistics):", "", "```", command.format(mode="--kernel-trace --stats", tag="kt", steps=5),
+             "```", "", "Counter runs (one counter each):", "", "```",
+             command.format(mode="--pmc FETCH_SIZE", tag="fetch", steps=2),
+             command.format(mode="--pmc WRITE_SIZE", tag="write", steps=2),
+             "```", "",
+             f"Counter calibration on the plain 256 MiB copy: FETCH_SIZE x {counters['FETCH_SIZE'][0]:.3f}, "
+             f"WRITE_SIZE x {counters['WRITE_SIZE'][0]:.3f} (scaled bytes below).", "",
+             "| kernel | calls | avg us | share % | HBM read MB/launch | HBM write MB/launch | GB/s |",
+             "|---|---|---|---|---|---|---|"]
+    for r in stats:
+        k = r["Name"]
+        avg_us = float(r["AverageNs"]) / 1e3
+        rd = counters["FETCH_SIZE"][1].get(k)
+        wr = counters["WRITE_SIZE"][1].get(k)
+        gbs = ((rd or 0) + (wr or 0)) / (avg_us * 1e-6) / 1e9 if rd is not None else None
+        lines.append(f"| {k} | {r['Calls']} | {avg_us:.1f} | {float(r['Percentage']):.2f} | "
+                     f"{'' if rd is None else f'{rd / 1e6:.1f}'} | {'' if wr is None else f'{wr / 1e6:.1f}'} | "
+                     f"{'' if gbs is None else f'{gbs:.0f}'} |")
+    lines += ["", "Machine-readable (bytes per launch, with the digest of the kernel's source file):", ""]
+    for k in STAGE_KERNEL.values():
+        rd = counters["FETCH_SIZE"][1].get(k)
+        wr = counters["WRITE_SIZE"][1].get(k)
+        if rd is not None and wr is not None:
+            lines.append(f"    traffic {k} read={rd:.0f} write={wr:.0f} source={source_digest(k)}")
+    open(out_md, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def profiled_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` from the committed profile summary, or
+    None if there is none or the kernel's source changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"nfsglft_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        parts = line.split()
+        if len(parts) == 5 and parts[0] == "traffic" and parts[1] == kernel:
+            kv = dict(p.split("=") for p in parts[2:])
+            if kv["source"] != source_digest(kernel):
+                return None
+            return float(kv["read"]) + float(kv["write"])
+    return None
+
+
 def main():
     a = parse()
+    if a.summarize:
+        summarize_profiles(*a.summarize, out_md=a.summary_out, command=PROFILE_COMMAND)
+        return
     if a.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported by this build "
               "(the transform shards over points, see DESIGN.md)", file=sys.stderr)
@@ -131,6 +224,16 @@ def main():
     plan_ms = (time.perf_counter() - t0) * 1e3
     info = plan.info()
     print(f"[bench] plan {plan_ms:.1f} ms, rho={plan.rho:.4f}, info={info}", file=sys.stderr, flush=True)
+
+    if a.copy_calibration > 0:
+        # a plain copy kernel of known size: reads and writes copy_calibration MiB each
+        src = torch.ones(a.copy_calibration * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        print(f"[bench] copy calibration: 3 x {a.copy_calibration} MiB", file=sys.stderr, flush=True)
 
     f = torch.empty(M, dtype=cdt, device="cuda")
     g = torch.empty(plan.nc, dtype=cdt, device="cuda")
@@ -163,8 +266,9 @@ def main():
         flops = spread_flops(q) * M
         peak = ALU_PEAK_F32_TFLOPS if prec == "f32" else ALU_PEAK_F64_TFLOPS
         achieved = flops / (avg[dom] * 1e-3) / 1e12
-        roof = {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": achieved / peak, "traffic": None}
+        roof = {"kernel": STAGE_KERNEL.get(dom, dom), "bound": "alu", "achieved": achieved, "peak": peak,
+                "unit": "TFLOP/s", "frac": achieved / peak,
+                "traffic": profiled_traffic(a.workload, STAGE_KERNEL.get(dom, dom))}
     else:
         byts = fb.get(dom, 0)
         achieved = byts / (avg[dom] * 1e-3) / 1e9
@@ -179,8 +283,10 @@ def main():
     f_host = f.cpu().numpy().astype(np.complex128)
     pts_used = pts.astype(np.float32).astype(np.float64) if prec == "f32" else pts
     fh_used = fh.astype(np.complex64).astype(np.complex128) if prec == "f32" else fh
-    acc = accuracy(B, plan, pts_used, fh_used, f_host, y, prec, a.check_points, torch, cdt)
-    print(f"[bench] accuracy {acc}", file=sys.stderr, flush=True)
+    acc = None
+    if a.check_points > 0:
+        acc = accuracy(B, plan, pts_used, fh_used, f_host, y, prec, a.check_points, torch, cdt)
+        print(f"[bench] accuracy {acc}", file=sys.stderr, flush=True)
 
     cpu = None
     if not a.no_cpu_baseline:
