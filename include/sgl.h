@@ -168,6 +168,10 @@ sgl_status sgl_plan_stage_times(sgl_plan_t plan, double ms[SGL_NUM_STAGES], int6
 /* Release the plan and its device memory (waits for its stream). */
 sgl_status sgl_destroy(sgl_plan_t plan);
 
+/* Name and description of the last HIP error this thread's calls turned into
+ * SGL_E_DEVICE or SGL_E_NOMEM (empty if none); valid until the next such error. */
+const char *sgl_last_error(void);
+
 /* Static description of a status code. */
 const char *sgl_status_string(sgl_status s);
 

@@ -20,6 +20,7 @@ SYMBOLS = (
     "sgl_num_coeffs", "sgl_coeff_index", "sgl_eta_dims", "sgl_plan", "sgl_forward", "sgl_adjoint",
     "sgl_conv_forward", "sgl_conv_adjoint", "sgl_nfft_forward", "sgl_nfft_adjoint", "sgl_plan_rho",
     "sgl_plan_info", "sgl_plan_profile", "sgl_plan_stage_times", "sgl_destroy", "sgl_status_string",
+    "sgl_last_error",
 )
 
 STAGES = ("conv_radial", "conv_polar", "fft_A", "fft_B", "fft_C", "gather", "scatter", "fft_Ch", "fft_Bh",
@@ -34,7 +35,10 @@ class SglParams(ctypes.Structure):
 class SglError(RuntimeError):
     def __init__(self, status, what):
         self.status = status
-        super().__init__(f"{what}: {status_string(status)} ({status})")
+        detail = ""
+        if status in (SGL_E_DEVICE, SGL_E_NOMEM):
+            detail = f" [{lib().sgl_last_error().decode()}]"
+        super().__init__(f"{what}: {status_string(status)} ({status}){detail}")
 
 
 _lib = None
@@ -63,6 +67,7 @@ def lib():
         L.sgl_plan_stage_times.restype = ctypes.c_int
         L.sgl_destroy.argtypes, L.sgl_destroy.restype = [vp], ctypes.c_int
         L.sgl_status_string.argtypes, L.sgl_status_string.restype = [ctypes.c_int], ctypes.c_char_p
+        L.sgl_last_error.argtypes, L.sgl_last_error.restype = [], ctypes.c_char_p
         _lib = L
     return _lib
 

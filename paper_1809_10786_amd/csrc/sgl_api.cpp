@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -22,8 +23,11 @@ namespace {
 constexpr double kPi = 3.141592653589793238462643383279502884;
 constexpr size_t kLdsBudget = 64 * 1024;
 
+thread_local char g_last_error[256] = "";
+
 sgl_status from_hip(hipError_t e) {
   if (e == hipSuccess) return SGL_OK;
+  snprintf(g_last_error, sizeof g_last_error, "%s: %s", hipGetErrorName(e), hipGetErrorString(e));
   if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return SGL_E_NOMEM;
   return SGL_E_DEVICE;
 }
@@ -555,6 +559,8 @@ sgl_status sgl_destroy(sgl_plan_t plan) {
   delete plan;
   return SGL_OK;
 }
+
+const char *sgl_last_error(void) { return g_last_error; }
 
 const char *sgl_status_string(sgl_status s) {
   switch (s) {

@@ -24,6 +24,8 @@
 //    in LDS; each workgroup owns a block of stored cells, accumulates in LDS
 //    the contributions of every point whose taps reach the block, and writes
 //    the block once.
+#include <type_traits>
+
 #include "sgl_internal.h"
 
 namespace sgl {
@@ -113,6 +115,193 @@ __global__ __launch_bounds__(256) void k_gather_tiled(const cplx<R> *__restrict_
       ai += w0 * bi;
     }
     f[perm[k]] = cplx<R>{ar, ai};
+  }
+}
+
+// ---------------------------------------------------------------- gather, MFMA
+
+// FP32 gather with the dimension-2 contraction on the matrix cores.  For one
+// chunk of one tile, the window box G[i0][i1][i2] is staged in LDS as four
+// FP16 planes (re/im x hi/lo with hi = fp16(s G), lo = fp16(s G - hi), s a
+// power of two that keeps the box inside FP16's range).  For every batch of 16
+// points, T[(i0, i1), p] = sum_i2 G[(i0, i1), i2] w2_p[i2] is a 368 x 16 x 32
+// product done as hi*hi + hi*lo + lo*hi on v_mfma_f32_16x16x32_f16 (FP32
+// accumulation; the dropped lo*lo term is ~2^-22 relative), and the remaining
+// sum f_p = sum_(i0,i1) w0_p[i0] w1_p[i1] T[(i0, i1), p] runs on the vector
+// units.  Weights are box-shifted: w_p[i] = gauss(frac + q - 1 - (i - o_p)) for
+// 0 <= i - o_p < 2q, zero elsewhere.  Requires L1 = L2 = 8 (X1 = X2 = Q2 + 7).
+typedef _Float16 sgl_half8 __attribute__((ext_vector_type(8)));
+typedef float sgl_float4 __attribute__((ext_vector_type(4)));
+
+constexpr int kPlaneK = 24;    // i2 slots per plane row (X2 <= 24); slots 24..31 of the MFMA K are zero
+constexpr int kWaveTab = 32;   // per-point weight table length (X0, X1 <= 32)
+
+constexpr int kMfmaThreads = 1024;  // 16 waves: four per SIMD hide LDS and matrix-core latency
+constexpr int kBoxPerThread = 8;    // box cells staged per thread (X0 X1 X2 <= 8192)
+constexpr int kTabStride = 68;      // floats per point in the weight tables
+
+template <int Q2>
+__global__ __launch_bounds__(kMfmaThreads) void k_gather_mfma(const cplx<float> *__restrict__ grid,
+                                                              const PointRec<float> *__restrict__ pts,
+                                                              const int32_t *__restrict__ perm,
+                                                              const int32_t *__restrict__ chunks, Geom g,
+                                                              float inv2lam, cplx<float> *__restrict__ f) {
+  constexpr int q = Q2 / 2;
+  constexpr int X1 = 8 + Q2 - 1, X2 = 8 + Q2 - 1;
+  constexpr int X1p = (X1 + 3) & ~3;  // rows padded so a lane's four D rows share i0
+  constexpr int NW = kMfmaThreads / 64;
+  static_assert(X2 <= kPlaneK, "box too long along dimension 2");
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const int X0 = g.X[0];
+  const int nrow = X0 * X1p;
+  const int nrb = (nrow + 15) / 16;
+  const int NR = nrb * 16;
+  _Float16 *plane = (_Float16 *)smem;  // [4][NR][kPlaneK]: re_hi, re_lo, im_hi, im_lo
+  // per point: w0 at [0, 32), w1 at [32, 64); the stride of kTabStride floats
+  // keeps the table reads and writes of a wave free of bank conflicts
+  float *wtab = (float *)(plane + 4 * NR * kPlaneK);  // [NW waves][16 points][kTabStride]
+  __shared__ float red[NW];
+  __shared__ int sidx0[kWaveTab], sidx1[kWaveTab], sidx2[kWaveTab];
+
+  const int tidx = chunks[3 * blockIdx.x];
+  const int start = chunks[3 * blockIdx.x + 1];
+  const int count = chunks[3 * blockIdx.x + 2];
+  const int c2 = tidx % g.T[2];
+  const int c1 = (tidx / g.T[2]) % g.T[1];
+  const int c0 = tidx / (g.T[2] * g.T[1]);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+
+  // 1. stored grid index of every box coordinate (-1: outside the stored grid)
+  if (threadIdx.x < kWaveTab) {
+    const int i = threadIdx.x;
+    sidx0[i] = i < X0 ? stored_index(c0 * g.L[0] - q + 1 + i, 0, g) : -1;
+    sidx1[i] = i < X1 ? stored_index(c1 * 8 - q + 1 + i, 1, g) : -1;
+    sidx2[i] = i < X2 ? stored_index(c2 * 8 - q + 1 + i, 2, g) : -1;
+  }
+  __syncthreads();
+  // 2. load the box once into registers, find its maximum
+  cplx<float> v[kBoxPerThread];
+  float mx = 0.0f;
+#pragma unroll
+  for (int u = 0; u < kBoxPerThread; ++u) {
+    const int e = threadIdx.x + u * kMfmaThreads;
+    v[u] = cplx<float>{0.0f, 0.0f};
+    if (e < X0 * X1 * X2) {
+      const int i2 = e % X2, r = e / X2, i1 = r % X1, i0 = r / X1;
+      const int s0 = sidx0[i0], s1 = sidx1[i1], s2 = sidx2[i2];
+      if (s0 >= 0 && s1 >= 0 && s2 >= 0) v[u] = grid[((size_t)s0 * g.E[1] + s1) * g.E[2] + s2];
+      mx = fmaxf(mx, fmaxf(fabsf(v[u].re), fabsf(v[u].im)));
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+  if (lane == 0) red[wave] = mx;
+  // zero the plane rows and K slots that the box does not fill
+  for (int e = threadIdx.x; e < NR * kPlaneK; e += kMfmaThreads) {
+    const int k = e % kPlaneK, r = e / kPlaneK;
+    if (k >= X2 || r >= nrow || r % X1p >= X1)
+      for (int pl = 0; pl < 4; ++pl) plane[pl * NR * kPlaneK + e] = (_Float16)0.0f;
+  }
+  __syncthreads();
+  float bmx = 0.0f;
+  for (int w = 0; w < NW; ++w) bmx = fmaxf(bmx, red[w]);
+  int ex = 0;
+  if (bmx > 0.0f) frexpf(bmx, &ex);     // bmx = m 2^ex, m in [0.5, 1)
+  const float sc = ldexpf(1.0f, 14 - ex);  // scaled maximum in [2^13, 2^14)
+  // 3. FP16 hi/lo planes
+#pragma unroll
+  for (int u = 0; u < kBoxPerThread; ++u) {
+    const int e = threadIdx.x + u * kMfmaThreads;
+    if (e < X0 * X1 * X2) {
+      const int i2 = e % X2, r = e / X2, i1 = r % X1, i0 = r / X1;
+      const int o = (i0 * X1p + i1) * kPlaneK + i2;
+      const float vr = v[u].re * sc, vi = v[u].im * sc;
+      const _Float16 rh = (_Float16)vr, ih = (_Float16)vi;
+      plane[o] = rh;
+      plane[NR * kPlaneK + o] = (_Float16)(vr - (float)rh);
+      plane[2 * NR * kPlaneK + o] = ih;
+      plane[3 * NR * kPlaneK + o] = (_Float16)(vi - (float)ih);
+    }
+  }
+  __syncthreads();
+
+  // 4. every wave walks its own batches of 16 points
+  const int pl = lane & 15, h = lane >> 4;
+  float *tab = wtab + (size_t)(wave * 16 + pl) * kTabStride;
+  const float kexp = -inv2lam * 1.4426950408889634f;
+  for (int b0 = wave * 16; b0 < count; b0 += NW * 16) {
+    const int k = start + b0 + pl;
+    const bool valid = b0 + pl < count;
+    PointRec<float> pr;
+    pr.frac[0] = pr.frac[1] = pr.frac[2] = 0.0f;
+    pr.cell = 0;
+    int o0 = 1 << 20, o1 = 1 << 20, o2 = 1 << 20;  // outside every box when invalid
+    if (valid) {
+      pr = pts[k];
+      o0 = cell0(pr.cell) - c0 * g.L[0];
+      o1 = cell1(pr.cell) - c1 * 8;
+      o2 = cell2(pr.cell) - c2 * 8;
+    }
+    // box-shifted w0 / w1 of this lane's point (the four lanes of a point split the work)
+    for (int i = h; i < kWaveTab; i += 4) {
+      const int t0 = i - o0, t1 = i - o1;
+      const float d0 = pr.frac[0] + (float)(q - 1 - t0), d1 = pr.frac[1] + (float)(q - 1 - t1);
+      tab[i] = ((unsigned)t0 < (unsigned)Q2) ? exp2f(d0 * d0 * kexp) : 0.0f;
+      tab[kWaveTab + i] = ((unsigned)t1 < (unsigned)Q2) ? exp2f(d1 * d1 * kexp) : 0.0f;
+    }
+    // B fragment: w2 of this lane's point at i2 = 8h + j (zero for h = 3)
+    sgl_half8 bh, bl;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int t2 = 8 * h + j - o2;
+      const float d2 = pr.frac[2] + (float)(q - 1 - t2);
+      const float w = (h < 3 && (unsigned)t2 < (unsigned)Q2) ? exp2f(d2 * d2 * kexp) : 0.0f;
+      const _Float16 wh = (_Float16)w;
+      bh[j] = wh;
+      bl[j] = (_Float16)(w - (float)wh);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    float ar = 0.0f, ai = 0.0f;
+    for (int rb = 0; rb < nrb; ++rb) {
+      const int arow = rb * 16 + pl;
+      sgl_half8 a0 = {}, a1 = {}, a2 = {}, a3 = {};
+      if (h < 3) {
+        const size_t off = (size_t)arow * kPlaneK + 8 * h;
+        a0 = *(const sgl_half8 *)(plane + off);
+        a1 = *(const sgl_half8 *)(plane + NR * kPlaneK + off);
+        a2 = *(const sgl_half8 *)(plane + 2 * NR * kPlaneK + off);
+        a3 = *(const sgl_half8 *)(plane + 3 * NR * kPlaneK + off);
+      }
+      // rows 4h .. 4h+3 of the block: one i0, i1 = i1b .. i1b+3
+      const int r4 = rb * 16 + 4 * h;
+      const int i0 = r4 / X1p, i1b = r4 - i0 * X1p;
+      const float w0 = (r4 < nrow) ? tab[i0] : 0.0f;
+      const sgl_float4 w1 = *(const sgl_float4 *)(tab + kWaveTab + i1b);
+      float cw[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) cw[j] = w0 * w1[j];
+      sgl_float4 dr = {0, 0, 0, 0}, di = {0, 0, 0, 0};
+      dr = __builtin_amdgcn_mfma_f32_16x16x32_f16(a0, bh, dr, 0, 0, 0);
+      di = __builtin_amdgcn_mfma_f32_16x16x32_f16(a2, bh, di, 0, 0, 0);
+      dr = __builtin_amdgcn_mfma_f32_16x16x32_f16(a0, bl, dr, 0, 0, 0);
+      di = __builtin_amdgcn_mfma_f32_16x16x32_f16(a2, bl, di, 0, 0, 0);
+      dr = __builtin_amdgcn_mfma_f32_16x16x32_f16(a1, bh, dr, 0, 0, 0);
+      di = __builtin_amdgcn_mfma_f32_16x16x32_f16(a3, bh, di, 0, 0, 0);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        ar += cw[j] * dr[j];
+        ai += cw[j] * di[j];
+      }
+    }
+    // the four lanes of a point hold disjoint rows: sum them
+    ar += __shfl_xor(ar, 16);
+    ai += __shfl_xor(ai, 16);
+    ar += __shfl_xor(ar, 32);
+    ai += __shfl_xor(ai, 32);
+    if (valid && h == 0) f[perm[k]] = cplx<float>{ar / sc, ai / sc};
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
   }
 }
 
@@ -607,6 +796,19 @@ template <class R, int Q2>
 hipError_t gather_q(const Plan &p, const void *grid, void *f) {
   const Geom g = make_geom(p);
   const R inv2lam = (R)(1.0 / (2.0 * p.lambda));
+  if constexpr (std::is_same<R, float>::value && Q2 <= 16) {
+    if (p.gather_mode == 0 && p.mfma && p.L[1] == 8 && p.L[2] == 8 &&
+        p.X[0] * p.X[1] * p.X[2] <= kMfmaThreads * kBoxPerThread && p.X[0] <= kWaveTab) {
+      const int nrow = p.X[0] * ((p.X[1] + 3) & ~3);
+      const size_t lds = (size_t)4 * ((nrow + 15) / 16 * 16) * kPlaneK * sizeof(_Float16) +
+                         (size_t)(kMfmaThreads / 64) * 16 * kTabStride * sizeof(float);
+      // gfx950 grants up to 160 KB of LDS per workgroup without an opt-in
+      k_gather_mfma<Q2><<<(unsigned)p.nchunks, kMfmaThreads, lds, p.stream>>>(
+          (const cplx<float> *)grid, (const PointRec<float> *)p.pts, p.perm, p.chunks, g, (float)inv2lam,
+          (cplx<float> *)f);
+      return hipGetLastError();
+    }
+  }
   if (p.gather_mode == 0) {
     const size_t lds = (size_t)p.X[0] * p.X[1] * p.X[2] * sizeof(cplx<R>);
     k_gather_tiled<R, Q2><<<(unsigned)p.nchunks, 256, lds, p.stream>>>(
