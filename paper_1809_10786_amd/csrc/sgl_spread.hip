@@ -629,6 +629,177 @@ __global__ __launch_bounds__(512) void k_spread_rows(const cplx<R> *__restrict__
   }
 }
 
+// Matrix-core form of the tiled spreading (FP32 data, tiles of 8^3 cells).
+// For the points of one chunk the window box of the tile is the product
+//   D[(i0, i1)][i2] = sum_p (w0_p[i0] w1_p[i1]) (f_p w2_p[i2]),
+// a contraction over the points: A[row][p] = w0 w1 (real), B[p][i2] = f_p w2
+// (one matrix for the real and one for the imaginary part), K = 32 points per
+// 16x16x32 FP16 product.  Both operands are split into FP16 hi + lo parts
+// (A scaled by 2^12, B by a power of two that puts the chunk's largest sample
+// into [2^13, 2^14)); hi*hi + hi*lo + lo*hi with FP32 accumulation keeps about
+// 22 significant bits.  Each of the 8 waves owns row blocks of 16 box rows for
+// the whole chunk, so the accumulators stay in registers until the box is
+// written to the staging area.
+constexpr int kSpreadThreads = 512;  // 8 waves
+constexpr int kSB = 128;             // points whose weight tables are staged at once
+constexpr int kTS = kSB + 4;         // floats per table row (conflict-free b128 reads)
+
+template <int Q2>
+__global__ __launch_bounds__(kSpreadThreads) void k_spread_mfma(const cplx<float> *__restrict__ y,
+                                                                const PointRec<float> *__restrict__ pts,
+                                                                const int32_t *__restrict__ perm,
+                                                                const int32_t *__restrict__ chunks, Geom g,
+                                                                float inv2lam, cplx<float> *__restrict__ staging) {
+  constexpr int q = Q2 / 2;
+  constexpr int X = 8 + Q2 - 1;  // box edge in every dimension
+  constexpr int nrow = X * X;
+  constexpr int nrb = (nrow + 15) / 16;
+  constexpr int NW = kSpreadThreads / 64;
+  constexpr int RBW = (nrb + NW - 1) / NW;
+  static_assert(X <= 32, "box edge exceeds two column blocks");
+  // tab[d][i][p]: w_d of point p at box index i (zero outside its window)
+  __shared__ __attribute__((aligned(16))) float tab[3][32][kTS];
+  __shared__ __attribute__((aligned(16))) float sfy[kSB][2];  // scaled samples
+  __shared__ float red[NW];
+
+  const int tidx = chunks[3 * blockIdx.x];
+  const int start = chunks[3 * blockIdx.x + 1];
+  const int count = chunks[3 * blockIdx.x + 2];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int pl = lane & 15, h = lane >> 4;
+
+  // power-of-two scale of the chunk's samples
+  float mx = 0.0f;
+  for (int k = threadIdx.x; k < count; k += kSpreadThreads) {
+    const cplx<float> v = y[perm[start + k]];
+    mx = fmaxf(mx, fmaxf(fabsf(v.re), fabsf(v.im)));
+  }
+  for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+  if (lane == 0) red[wave] = mx;
+  __syncthreads();
+  float bmx = 0.0f;
+  for (int w = 0; w < NW; ++w) bmx = fmaxf(bmx, red[w]);
+  int ex = 0;
+  if (bmx > 0.0f) frexpf(bmx, &ex);
+  const float sc = ldexpf(1.0f, 14 - ex);
+  const float kexp = -inv2lam * 1.4426950408889634f;
+
+  sgl_float4 acc[RBW][2][2];
+#pragma unroll
+  for (int r = 0; r < RBW; ++r)
+#pragma unroll
+    for (int n = 0; n < 2; ++n) acc[r][n][0] = acc[r][n][1] = sgl_float4{0.0f, 0.0f, 0.0f, 0.0f};
+
+  for (int b0 = 0; b0 < count; b0 += kSB) {
+    __syncthreads();  // the previous batch's tables are consumed
+    if ((int)threadIdx.x < 3 * kSB) {
+      const int d = threadIdx.x / kSB, pp = threadIdx.x % kSB;
+      float fr = 0.0f;
+      int o = 1 << 20;  // outside every box when the point is absent
+      if (b0 + pp < count) {
+        const PointRec<float> pr = pts[start + b0 + pp];
+        fr = d == 0 ? pr.frac[0] : (d == 1 ? pr.frac[1] : pr.frac[2]);
+        const int cell = d == 0 ? cell0(pr.cell) : (d == 1 ? cell1(pr.cell) : cell2(pr.cell));
+        const int c = d == 0 ? tidx / (g.T[2] * g.T[1]) : (d == 1 ? (tidx / g.T[2]) % g.T[1] : tidx % g.T[2]);
+        o = cell - c * 8;
+      }
+      // w0 and w1 carry 2^6 each (A = 2^12 w0 w1 <= 2^12); w2 is unscaled so
+      // that B = f w2 stays below 2^14, inside the FP16 range
+      const float lsc = d < 2 ? 6.0f : 0.0f;
+      for (int i = 0; i < 32; ++i) {
+        const int t = i - o;
+        const float dd = fr + (float)(q - 1 - t);
+        tab[d][i][pp] = ((unsigned)t < (unsigned)Q2) ? exp2f(dd * dd * kexp + lsc) : 0.0f;
+      }
+    } else {
+      const int pp = threadIdx.x - 3 * kSB;
+      cplx<float> v = {0.0f, 0.0f};
+      if (b0 + pp < count) v = y[perm[start + b0 + pp]];
+      sfy[pp][0] = v.re * sc;
+      sfy[pp][1] = v.im * sc;
+    }
+    __syncthreads();
+    const int nb = min(kSB, count - b0);
+    for (int ks = 0; ks < nb; ks += 32) {
+      const int p0 = ks + 8 * h;  // this lane's 8 points of the K step
+      float fre[8], fim[8];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const sgl_float4 v = *(const sgl_float4 *)&sfy[p0 + 2 * i][0];
+        fre[2 * i] = v[0];
+        fim[2 * i] = v[1];
+        fre[2 * i + 1] = v[2];
+        fim[2 * i + 1] = v[3];
+      }
+      // B fragments: column i2 = 16 n + pl, points p0 .. p0 + 7
+      sgl_half8 brh[2], brl[2], bih[2], bil[2];
+#pragma unroll
+      for (int n = 0; n < 2; ++n) {
+        const float *w2 = &tab[2][16 * n + pl][p0];
+        const sgl_float4 wa = *(const sgl_float4 *)w2, wb = *(const sgl_float4 *)(w2 + 4);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const float w = i < 4 ? wa[i] : wb[i - 4];
+          const float br = fre[i] * w, bi = fim[i] * w;
+          const _Float16 rh = (_Float16)br, ih = (_Float16)bi;
+          brh[n][i] = rh;
+          brl[n][i] = (_Float16)(br - (float)rh);
+          bih[n][i] = ih;
+          bil[n][i] = (_Float16)(bi - (float)ih);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < RBW; ++r) {
+        const int rb = wave + r * NW;
+        if (rb < nrb) {
+          const int row = rb * 16 + pl;
+          const int i0 = row / X, i1 = row - (row / X) * X;  // i0 <= X + 15 / X < 32
+          const float *t0 = &tab[0][i0][p0], *t1 = &tab[1][i1][p0];
+          const sgl_float4 ua = *(const sgl_float4 *)t0, ub = *(const sgl_float4 *)(t0 + 4);
+          const sgl_float4 va = *(const sgl_float4 *)t1, vb = *(const sgl_float4 *)(t1 + 4);
+          sgl_half8 ah, al;
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            const float a = row < nrow ? (i < 4 ? ua[i] * va[i] : ub[i - 4] * vb[i - 4]) : 0.0f;
+            const _Float16 hh = (_Float16)a;
+            ah[i] = hh;
+            al[i] = (_Float16)(a - (float)hh);
+          }
+#pragma unroll
+          for (int n = 0; n < 2; ++n) {
+            acc[r][n][0] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, brh[n], acc[r][n][0], 0, 0, 0);
+            acc[r][n][1] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bih[n], acc[r][n][1], 0, 0, 0);
+            acc[r][n][0] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, brl[n], acc[r][n][0], 0, 0, 0);
+            acc[r][n][1] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bil[n], acc[r][n][1], 0, 0, 0);
+            acc[r][n][0] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, brh[n], acc[r][n][0], 0, 0, 0);
+            acc[r][n][1] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bih[n], acc[r][n][1], 0, 0, 0);
+          }
+        }
+      }
+    }
+  }
+  // D[4h + j][pl] of every row block to the chunk's box in the staging area
+  const float inv = 1.0f / (4096.0f * sc);
+  cplx<float> *out = staging + (size_t)blockIdx.x * nrow * X;
+#pragma unroll
+  for (int r = 0; r < RBW; ++r) {
+    const int rb = wave + r * NW;
+    if (rb < nrb) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = rb * 16 + 4 * h + j;
+        if (row < nrow) {
+#pragma unroll
+          for (int n = 0; n < 2; ++n) {
+            const int col = 16 * n + pl;
+            if (col < X) out[row * X + col] = cplx<float>{acc[r][n][0][j] * inv, acc[r][n][1][j] * inv};
+          }
+        }
+      }
+    }
+  }
+}
+
 constexpr int kMaxCand = 256;
 
 // Sum of the staged window boxes into the stored grid: one workgroup per
@@ -824,6 +995,14 @@ template <class R, int Q2>
 hipError_t scatter_q(const Plan &p, const void *f, void *grid) {
   const Geom g = make_geom(p);
   const R inv2lam = (R)(1.0 / (2.0 * p.lambda));
+  if constexpr (std::is_same<R, float>::value && Q2 <= 16) {
+    if (p.gather_mode == 0 && p.mfma && p.L[0] == 8 && p.L[1] == 8 && p.L[2] == 8) {
+      k_spread_mfma<Q2><<<(unsigned)p.nchunks, kSpreadThreads, 0, p.stream>>>(
+          (const cplx<float> *)f, (const PointRec<float> *)p.pts, p.perm, p.chunks, g, (float)inv2lam,
+          (cplx<float> *)p.staging);
+      return hipGetLastError();
+    }
+  }
   if (p.gather_mode == 0) {
     if constexpr (Q2 <= 16) {
       const unsigned threads = (unsigned)((p.X[0] * p.X[1] + 63) / 64 * 64);
