@@ -635,14 +635,40 @@ __global__ __launch_bounds__(512) void k_spread_rows(const cplx<R> *__restrict__
 // a contraction over the points: A[row][p] = w0 w1 (real), B[p][i2] = f_p w2
 // (one matrix for the real and one for the imaginary part), K = 32 points per
 // 16x16x32 FP16 product.  Both operands are split into FP16 hi + lo parts
-// (A scaled by 2^12, B by a power of two that puts the chunk's largest sample
-// into [2^13, 2^14)); hi*hi + hi*lo + lo*hi with FP32 accumulation keeps about
-// 22 significant bits.  Each of the 8 waves owns row blocks of 16 box rows for
-// the whole chunk, so the accumulators stay in registers until the box is
-// written to the staging area.
-constexpr int kSpreadThreads = 512;  // 8 waves
-constexpr int kSB = 128;             // points whose weight tables are staged at once
-constexpr int kTS = kSB + 4;         // floats per table row (conflict-free b128 reads)
+// (A scaled by 2^12, B by a power of two that puts the largest sample seen so
+// far into [2^13, 2^14); when a later batch raises it, the accumulators are
+// rescaled by the exact power of two).  hi*hi + hi*lo + lo*hi with FP32
+// accumulation keeps about 22 significant bits.
+// Per batch of kSB points the workgroup stages the w0 and w1 tables and the
+// four FP16 planes of B in LDS; each of the 4 waves then owns row blocks of 16
+// box rows for the whole chunk and forms its own A fragments, so the
+// accumulators stay in registers until the box is written to the staging
+// area.  Two workgroups share a compute unit, so one stages its tables while
+// the other multiplies, and the point records and samples of the next batch
+// are loaded while the current one is multiplied.
+constexpr int kSpreadThreads = 256;  // 4 waves
+constexpr int kSB = 128;             // points staged at once
+constexpr int kTS = kSB + 4;         // floats per weight-table row (conflict-free b128 reads)
+constexpr int kBS = kSB + 8;         // halves per B-plane column (conflict-free b128 reads)
+constexpr int kNoExp = -100;         // running exponent before the first nonzero sample
+
+typedef float sgl_float2 __attribute__((ext_vector_type(2)));
+typedef _Float16 sgl_half2 __attribute__((ext_vector_type(2)));
+
+// FP16 hi + lo parts of eight FP32 values (hi rounded to nearest, lo = the
+// rounded remainder)
+__device__ inline void split8(const float (&v)[8], sgl_half8 &hi, sgl_half8 &lo) {
+#pragma unroll
+  for (int i = 0; i < 8; i += 2) {
+    const sgl_half2 hh = __builtin_convertvector(sgl_float2{v[i], v[i + 1]}, sgl_half2);
+    const sgl_half2 ll =
+        __builtin_convertvector(sgl_float2{v[i] - (float)hh[0], v[i + 1] - (float)hh[1]}, sgl_half2);
+    hi[i] = hh[0];
+    hi[i + 1] = hh[1];
+    lo[i] = ll[0];
+    lo[i + 1] = ll[1];
+  }
+}
 
 template <int Q2>
 __global__ __launch_bounds__(kSpreadThreads) void k_spread_mfma(const cplx<float> *__restrict__ y,
@@ -657,114 +683,157 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_mfma(const cplx<float
   constexpr int NW = kSpreadThreads / 64;
   constexpr int RBW = (nrb + NW - 1) / NW;
   static_assert(X <= 32, "box edge exceeds two column blocks");
-  // tab[d][i][p]: w_d of point p at box index i (zero outside its window)
-  __shared__ __attribute__((aligned(16))) float tab[3][32][kTS];
-  __shared__ __attribute__((aligned(16))) float sfy[kSB][2];  // scaled samples
-  __shared__ float red[NW];
+  static_assert(2 * kSB == kSpreadThreads, "two threads per point");
+  // tab[d][i][p]: 64 w_d of point p at box index i, d = 0, 1; zero outside
+  // the point's window, in particular for i >= X (rows past the box)
+  __shared__ __attribute__((aligned(16))) float tab[2][32][kTS];
+  // bpl[plane][i2][p]: FP16 parts of B (re hi, re lo, im hi, im lo)
+  __shared__ __attribute__((aligned(16))) _Float16 bpl[4][32][kBS];
+  __shared__ __attribute__((aligned(16))) float sfy[kSB][2];  // samples of the batch
+  __shared__ float sfr2[kSB];                                 // fractional position along dimension 2
+  __shared__ int so2[kSB];                                    // window start along dimension 2 in the box
+  __shared__ int red[2];                                      // exponents of the loader waves' maxima
 
   const int tidx = chunks[3 * blockIdx.x];
   const int start = chunks[3 * blockIdx.x + 1];
   const int count = chunks[3 * blockIdx.x + 2];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int pl = lane & 15, h = lane >> 4;
-
-  // power-of-two scale of the chunk's samples
-  float mx = 0.0f;
-  for (int k = threadIdx.x; k < count; k += kSpreadThreads) {
-    const cplx<float> v = y[perm[start + k]];
-    mx = fmaxf(mx, fmaxf(fabsf(v.re), fabsf(v.im)));
-  }
-  for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
-  if (lane == 0) red[wave] = mx;
-  __syncthreads();
-  float bmx = 0.0f;
-  for (int w = 0; w < NW; ++w) bmx = fmaxf(bmx, red[w]);
-  int ex = 0;
-  if (bmx > 0.0f) frexpf(bmx, &ex);
-  const float sc = ldexpf(1.0f, 14 - ex);
+  // thread roles while staging: point pp; role 0 builds w0 and the dimension-2
+  // data, role 1 builds w1 and loads the sample
+  const int role = threadIdx.x / kSB, pp = threadIdx.x % kSB;
+  const int c0 = tidx / (g.T[2] * g.T[1]), c1 = (tidx / g.T[2]) % g.T[1], c2 = tidx % g.T[2];
+  const int ct = role == 0 ? c0 : c1;
   const float kexp = -inv2lam * 1.4426950408889634f;
+
+  // registers holding the next batch
+  bool nvalid = false;
+  PointRec<float> npr;
+  npr.frac[0] = npr.frac[1] = npr.frac[2] = 0.0f;
+  npr.cell = 0;
+  cplx<float> ny = {0.0f, 0.0f};
+  auto fetch = [&](int b0) {
+    nvalid = b0 + pp < count;
+    if (nvalid) {
+      npr = pts[start + b0 + pp];
+      if (role == 1) ny = y[perm[start + b0 + pp]];
+    }
+  };
+  fetch(0);
 
   sgl_float4 acc[RBW][2][2];
 #pragma unroll
   for (int r = 0; r < RBW; ++r)
 #pragma unroll
     for (int n = 0; n < 2; ++n) acc[r][n][0] = acc[r][n][1] = sgl_float4{0.0f, 0.0f, 0.0f, 0.0f};
+  int E = kNoExp;
+  float sc = 1.0f;
 
   for (int b0 = 0; b0 < count; b0 += kSB) {
-    __syncthreads();  // the previous batch's tables are consumed
-    if ((int)threadIdx.x < 3 * kSB) {
-      const int d = threadIdx.x / kSB, pp = threadIdx.x % kSB;
-      float fr = 0.0f;
-      int o = 1 << 20;  // outside every box when the point is absent
-      if (b0 + pp < count) {
-        const PointRec<float> pr = pts[start + b0 + pp];
-        fr = d == 0 ? pr.frac[0] : (d == 1 ? pr.frac[1] : pr.frac[2]);
-        const int cell = d == 0 ? cell0(pr.cell) : (d == 1 ? cell1(pr.cell) : cell2(pr.cell));
-        const int c = d == 0 ? tidx / (g.T[2] * g.T[1]) : (d == 1 ? (tidx / g.T[2]) % g.T[1] : tidx % g.T[2]);
-        o = cell - c * 8;
+    // 1. weight tables of dimensions 0 and 1, window data of dimension 2, samples
+    {
+      const float fr = role == 0 ? npr.frac[0] : npr.frac[1];
+      const int cell = role == 0 ? cell0(npr.cell) : cell1(npr.cell);
+#pragma unroll
+      for (int i = 0; i < 32; ++i) tab[role][i][pp] = 0.0f;
+      if (nvalid) {
+        const int o = cell - ct * 8;  // in [0, 8): the point lies in this tile
+#pragma unroll
+        for (int t = 0; t < Q2; ++t) {
+          const float dd = fr + (float)(q - 1 - t);
+          tab[role][o + t][pp] = exp2f(dd * dd * kexp + 6.0f);
+        }
       }
-      // w0 and w1 carry 2^6 each (A = 2^12 w0 w1 <= 2^12); w2 is unscaled so
-      // that B = f w2 stays below 2^14, inside the FP16 range
-      const float lsc = d < 2 ? 6.0f : 0.0f;
-      for (int i = 0; i < 32; ++i) {
-        const int t = i - o;
-        const float dd = fr + (float)(q - 1 - t);
-        tab[d][i][pp] = ((unsigned)t < (unsigned)Q2) ? exp2f(dd * dd * kexp + lsc) : 0.0f;
+      if (role == 0) {
+        sfr2[pp] = npr.frac[2];
+        so2[pp] = nvalid ? cell2(npr.cell) - c2 * 8 : (1 << 20);
+      } else {
+        const cplx<float> v = nvalid ? ny : cplx<float>{0.0f, 0.0f};
+        sfy[pp][0] = v.re;
+        sfy[pp][1] = v.im;
+        float mx = fmaxf(fabsf(v.re), fabsf(v.im));
+        for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+        int ex = kNoExp;
+        if (mx > 0.0f) frexpf(mx, &ex);
+        if (lane == 0) red[wave - kSB / 64] = max(ex, kNoExp);
       }
-    } else {
-      const int pp = threadIdx.x - 3 * kSB;
-      cplx<float> v = {0.0f, 0.0f};
-      if (b0 + pp < count) v = y[perm[start + b0 + pp]];
-      sfy[pp][0] = v.re * sc;
-      sfy[pp][1] = v.im * sc;
     }
     __syncthreads();
     const int nb = min(kSB, count - b0);
+    if (b0 + kSB < count) fetch(b0 + kSB);
+    {
+      const int eb = max(red[0], red[1]);
+      if (eb > E) {
+        if (E > kNoExp) {
+          const float f = ldexpf(1.0f, E - eb);
+#pragma unroll
+          for (int r = 0; r < RBW; ++r)
+#pragma unroll
+            for (int n = 0; n < 2; ++n)
+#pragma unroll
+              for (int j = 0; j < 4; ++j) {
+                acc[r][n][0][j] *= f;
+                acc[r][n][1][j] *= f;
+              }
+        }
+        E = eb;
+        sc = ldexpf(1.0f, 14 - E);
+      }
+    }
+    // 2. B planes: work item -> column c = i2, points 8 pg .. 8 pg + 7
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+      const int wi = threadIdx.x + it * kSpreadThreads;
+      const int c = wi / (kSB / 8), pg = wi % (kSB / 8);
+      float br[8], bi[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int pt = 8 * pg + i;
+        const int t = c - so2[pt];
+        const float dd = sfr2[pt] + (float)(q - 1 - t);
+        const float w = ((unsigned)t < (unsigned)Q2) ? exp2f(dd * dd * kexp) * sc : 0.0f;
+        br[i] = sfy[pt][0] * w;
+        bi[i] = sfy[pt][1] * w;
+      }
+      sgl_half8 rh, rl, ih, il;
+      split8(br, rh, rl);
+      split8(bi, ih, il);
+      *(sgl_half8 *)&bpl[0][c][8 * pg] = rh;
+      *(sgl_half8 *)&bpl[1][c][8 * pg] = rl;
+      *(sgl_half8 *)&bpl[2][c][8 * pg] = ih;
+      *(sgl_half8 *)&bpl[3][c][8 * pg] = il;
+    }
+    __syncthreads();
+    // 3. products over the batch, K = 32 points per step
     for (int ks = 0; ks < nb; ks += 32) {
       const int p0 = ks + 8 * h;  // this lane's 8 points of the K step
-      float fre[8], fim[8];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const sgl_float4 v = *(const sgl_float4 *)&sfy[p0 + 2 * i][0];
-        fre[2 * i] = v[0];
-        fim[2 * i] = v[1];
-        fre[2 * i + 1] = v[2];
-        fim[2 * i + 1] = v[3];
-      }
-      // B fragments: column i2 = 16 n + pl, points p0 .. p0 + 7
       sgl_half8 brh[2], brl[2], bih[2], bil[2];
 #pragma unroll
       for (int n = 0; n < 2; ++n) {
-        const float *w2 = &tab[2][16 * n + pl][p0];
-        const sgl_float4 wa = *(const sgl_float4 *)w2, wb = *(const sgl_float4 *)(w2 + 4);
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          const float w = i < 4 ? wa[i] : wb[i - 4];
-          const float br = fre[i] * w, bi = fim[i] * w;
-          const _Float16 rh = (_Float16)br, ih = (_Float16)bi;
-          brh[n][i] = rh;
-          brl[n][i] = (_Float16)(br - (float)rh);
-          bih[n][i] = ih;
-          bil[n][i] = (_Float16)(bi - (float)ih);
-        }
+        const int c = 16 * n + pl;
+        brh[n] = *(const sgl_half8 *)&bpl[0][c][p0];
+        brl[n] = *(const sgl_half8 *)&bpl[1][c][p0];
+        bih[n] = *(const sgl_half8 *)&bpl[2][c][p0];
+        bil[n] = *(const sgl_half8 *)&bpl[3][c][p0];
       }
 #pragma unroll
       for (int r = 0; r < RBW; ++r) {
         const int rb = wave + r * NW;
         if (rb < nrb) {
+          // A fragment: row rb * 16 + pl, points p0 .. p0 + 7
           const int row = rb * 16 + pl;
           const int i0 = row / X, i1 = row - (row / X) * X;  // i0 <= X + 15 / X < 32
           const float *t0 = &tab[0][i0][p0], *t1 = &tab[1][i1][p0];
           const sgl_float4 ua = *(const sgl_float4 *)t0, ub = *(const sgl_float4 *)(t0 + 4);
           const sgl_float4 va = *(const sgl_float4 *)t1, vb = *(const sgl_float4 *)(t1 + 4);
-          sgl_half8 ah, al;
+          float a[8];
 #pragma unroll
-          for (int i = 0; i < 8; ++i) {
-            const float a = row < nrow ? (i < 4 ? ua[i] * va[i] : ub[i - 4] * vb[i - 4]) : 0.0f;
-            const _Float16 hh = (_Float16)a;
-            ah[i] = hh;
-            al[i] = (_Float16)(a - (float)hh);
+          for (int i = 0; i < 4; ++i) {
+            a[i] = ua[i] * va[i];
+            a[i + 4] = ub[i] * vb[i];
           }
+          sgl_half8 ah, al;
+          split8(a, ah, al);
 #pragma unroll
           for (int n = 0; n < 2; ++n) {
             acc[r][n][0] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, brh[n], acc[r][n][0], 0, 0, 0);
@@ -777,6 +846,7 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_mfma(const cplx<float
         }
       }
     }
+    __syncthreads();  // the batch's tables are consumed
   }
   // D[4h + j][pl] of every row block to the chunk's box in the staging area
   const float inv = 1.0f / (4096.0f * sc);
