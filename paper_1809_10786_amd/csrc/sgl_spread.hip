@@ -120,87 +120,107 @@ __global__ __launch_bounds__(256) void k_gather_tiled(const cplx<R> *__restrict_
 
 // ---------------------------------------------------------------- gather, MFMA
 
-// FP32 gather with the dimension-2 contraction on the matrix cores.  For one
-// chunk of one tile, the window box G[i0][i1][i2] is staged in LDS as four
-// FP16 planes (re/im x hi/lo with hi = fp16(s G), lo = fp16(s G - hi), s a
-// power of two that keeps the box inside FP16's range).  For every batch of 16
-// points, T[(i0, i1), p] = sum_i2 G[(i0, i1), i2] w2_p[i2] is a 368 x 16 x 32
-// product done as hi*hi + hi*lo + lo*hi on v_mfma_f32_16x16x32_f16 (FP32
-// accumulation; the dropped lo*lo term is ~2^-22 relative), and the remaining
-// sum f_p = sum_(i0,i1) w0_p[i0] w1_p[i1] T[(i0, i1), p] runs on the vector
-// units.  Weights are box-shifted: w_p[i] = gauss(frac + q - 1 - (i - o_p)) for
-// 0 <= i - o_p < 2q, zero elsewhere.  Requires L1 = L2 = 8 (X1 = X2 = Q2 + 7).
+// FP32 gather with the dimension-2 contraction on the matrix cores (tiles of
+// 8^3 cells).  For one chunk of one tile, the window box G[i0][i1][i2] is
+// staged in LDS as four FP16 planes (re/im x hi/lo with hi = fp16(s G),
+// lo = fp16(s G - hi), s a power of two that puts the box maximum into
+// [2^13, 2^14)).  Rows are (i0, i1) with i1 padded to a multiple of 4, so the
+// four D rows of a lane share one i0.  For every group of 16 points,
+// T[(i0, i1), p] = sum_i2 G[(i0, i1), i2] w2_p[i2] is a rows x 16 x 32 product
+// done as hi*hi + hi*lo + lo*hi on v_mfma_f32_16x16x32_f16 (FP32 accumulation;
+// the dropped lo*lo term is ~2^-22 relative), and the remaining sum
+// f_p = sum_(i0,i1) w0_p[i0] w1_p[i1] T[(i0, i1), p] runs on the vector units.
+// Each wave takes passes of two groups, so every A fragment read from LDS
+// serves 32 points.  Weights are box-shifted: w_p[i] = gauss(frac + q - 1 -
+// (i - o_p)) for 0 <= i - o_p < 2q, zero elsewhere (also past the box).
 typedef _Float16 sgl_half8 __attribute__((ext_vector_type(8)));
+typedef _Float16 sgl_half2 __attribute__((ext_vector_type(2)));
 typedef float sgl_float4 __attribute__((ext_vector_type(4)));
+typedef float sgl_float2 __attribute__((ext_vector_type(2)));
 
-constexpr int kPlaneK = 24;    // i2 slots per plane row (X2 <= 24); slots 24..31 of the MFMA K are zero
-constexpr int kWaveTab = 32;   // per-point weight table length (X0, X1 <= 32)
-
-constexpr int kMfmaThreads = 1024;  // 16 waves: four per SIMD hide LDS and matrix-core latency
-constexpr int kBoxPerThread = 8;    // box cells staged per thread (X0 X1 X2 <= 8192)
-constexpr int kTabStride = 68;      // floats per point in the weight tables
+constexpr int kPlaneK = 24;  // i2 slots per plane row; MFMA K slots 24..31 meet zero weights
+constexpr int kLdsMax = 160 * 1024;
 
 template <int Q2>
-__global__ __launch_bounds__(kMfmaThreads) void k_gather_mfma(const cplx<float> *__restrict__ grid,
-                                                              const PointRec<float> *__restrict__ pts,
-                                                              const int32_t *__restrict__ perm,
-                                                              const int32_t *__restrict__ chunks, Geom g,
-                                                              float inv2lam, cplx<float> *__restrict__ f) {
-  constexpr int q = Q2 / 2;
-  constexpr int X1 = 8 + Q2 - 1, X2 = 8 + Q2 - 1;
-  constexpr int X1p = (X1 + 3) & ~3;  // rows padded so a lane's four D rows share i0
-  constexpr int NW = kMfmaThreads / 64;
-  static_assert(X2 <= kPlaneK, "box too long along dimension 2");
+struct GatherShape {
+  static constexpr int X = 7 + Q2;          // box edge
+  static constexpr int X1p = (X + 3) & ~3;  // padded i1 extent of a row group
+  static constexpr int nrow = X * X1p;
+  static constexpr int nrb = (nrow + 15) / 16;
+  static constexpr int NR = nrb * 16;
+  static constexpr int S = ((X1p / 4) % 2 == 0) ? X1p + 4 : X1p;  // w1 floats per point: odd multiple of 4
+  static constexpr size_t plane_bytes = (size_t)4 * NR * kPlaneK * sizeof(_Float16);
+  static constexpr size_t tab_bytes(int waves) { return (size_t)waves * 32 * S * sizeof(float); }
+  // as many waves as LDS allows (16, 12 or 8); static LDS of the kernel is below 1 KB
+  static constexpr int waves = plane_bytes + tab_bytes(16) + 1024 <= kLdsMax   ? 16
+                               : plane_bytes + tab_bytes(12) + 1024 <= kLdsMax ? 12
+                                                                               : 8;
+  static constexpr int threads = 64 * waves;
+  static constexpr int items = NR * (kPlaneK / 2);  // staged pairs of i2 slots
+  static constexpr int KB = (items + threads - 1) / threads;
+  static constexpr size_t lds = plane_bytes + tab_bytes(waves);
+};
+
+template <int Q2>
+__global__ __launch_bounds__(GatherShape<Q2>::threads) void k_gather_mfma(const cplx<float> *__restrict__ grid,
+                                                                          const PointRec<float> *__restrict__ pts,
+                                                                          const int32_t *__restrict__ perm,
+                                                                          const int32_t *__restrict__ chunks,
+                                                                          Geom g, float inv2lam,
+                                                                          cplx<float> *__restrict__ f) {
+  using Sh = GatherShape<Q2>;
+  constexpr int q = Q2 / 2, X = Sh::X, X1p = Sh::X1p, NR = Sh::NR, S = Sh::S;
+  constexpr int NW = Sh::waves, NT = Sh::threads;
+  constexpr int PS = NR * kPlaneK;      // halves per plane
+  constexpr int UR = (Q2 >= 10 && Q2 < 16) ? 2 : 1;  // row blocks in flight per wave (as registers allow)
+  static_assert(X <= kPlaneK, "box too long along dimension 2");
+  static_assert(Sh::lds + 1024 <= kLdsMax, "LDS budget");
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  const int X0 = g.X[0];
-  const int nrow = X0 * X1p;
-  const int nrb = (nrow + 15) / 16;
-  const int NR = nrb * 16;
-  _Float16 *plane = (_Float16 *)smem;  // [4][NR][kPlaneK]: re_hi, re_lo, im_hi, im_lo
-  // per point: w0 at [0, 32), w1 at [32, 64); the stride of kTabStride floats
-  // keeps the table reads and writes of a wave free of bank conflicts
-  float *wtab = (float *)(plane + 4 * NR * kPlaneK);  // [NW waves][16 points][kTabStride]
+  _Float16 *plane = (_Float16 *)smem;       // [4][NR][kPlaneK]: re_hi, re_lo, im_hi, im_lo
+  float *wtab = (float *)(plane + 4 * PS);  // [NW][32 points][S]: w1 at [0, X1p)
   __shared__ float red[NW];
-  __shared__ int sidx0[kWaveTab], sidx1[kWaveTab], sidx2[kWaveTab];
+  __shared__ int sidx[3][32];
 
   const int tidx = chunks[3 * blockIdx.x];
   const int start = chunks[3 * blockIdx.x + 1];
   const int count = chunks[3 * blockIdx.x + 2];
-  const int c2 = tidx % g.T[2];
-  const int c1 = (tidx / g.T[2]) % g.T[1];
-  const int c0 = tidx / (g.T[2] * g.T[1]);
+  const int c0 = tidx / (g.T[2] * g.T[1]), c1 = (tidx / g.T[2]) % g.T[1], c2 = tidx % g.T[2];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 
   // 1. stored grid index of every box coordinate (-1: outside the stored grid)
-  if (threadIdx.x < kWaveTab) {
-    const int i = threadIdx.x;
-    sidx0[i] = i < X0 ? stored_index(c0 * g.L[0] - q + 1 + i, 0, g) : -1;
-    sidx1[i] = i < X1 ? stored_index(c1 * 8 - q + 1 + i, 1, g) : -1;
-    sidx2[i] = i < X2 ? stored_index(c2 * 8 - q + 1 + i, 2, g) : -1;
+  if (threadIdx.x < 96) {
+    const int d = threadIdx.x / 32, i = threadIdx.x % 32;
+    const int cd = d == 0 ? c0 : (d == 1 ? c1 : c2);
+    sidx[d][i] = i < X ? stored_index(cd * 8 - q + 1 + i, d, g) : -1;
   }
   __syncthreads();
-  // 2. load the box once into registers, find its maximum
-  cplx<float> v[kBoxPerThread];
+  // 2. the box (with its zero padding) in registers, pairs of i2 slots per item
+  cplx<float> v[Sh::KB][2];
   float mx = 0.0f;
 #pragma unroll
-  for (int u = 0; u < kBoxPerThread; ++u) {
-    const int e = threadIdx.x + u * kMfmaThreads;
-    v[u] = cplx<float>{0.0f, 0.0f};
-    if (e < X0 * X1 * X2) {
-      const int i2 = e % X2, r = e / X2, i1 = r % X1, i0 = r / X1;
-      const int s0 = sidx0[i0], s1 = sidx1[i1], s2 = sidx2[i2];
-      if (s0 >= 0 && s1 >= 0 && s2 >= 0) v[u] = grid[((size_t)s0 * g.E[1] + s1) * g.E[2] + s2];
-      mx = fmaxf(mx, fmaxf(fabsf(v[u].re), fabsf(v[u].im)));
+  for (int u = 0; u < Sh::KB; ++u) {
+    const int e = threadIdx.x + u * NT;
+    v[u][0] = v[u][1] = cplx<float>{0.0f, 0.0f};
+    if (e < Sh::items) {
+      const int r = e / (kPlaneK / 2), kp = e % (kPlaneK / 2);
+      const int i0 = r / X1p, i1 = r % X1p;
+      if (i0 < X && i1 < X) {
+        const int s0 = sidx[0][i0], s1 = sidx[1][i1];
+        if (s0 >= 0 && s1 >= 0) {
+          const size_t base = ((size_t)s0 * g.E[1] + s1) * g.E[2];
+#pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            const int k = 2 * kp + c;
+            const int s2 = k < X ? sidx[2][k] : -1;
+            if (s2 >= 0) v[u][c] = grid[base + s2];
+          }
+        }
+      }
+      mx = fmaxf(mx, fmaxf(fmaxf(fabsf(v[u][0].re), fabsf(v[u][0].im)), fmaxf(fabsf(v[u][1].re), fabsf(v[u][1].im))));
     }
   }
   for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
   if (lane == 0) red[wave] = mx;
-  // zero the plane rows and K slots that the box does not fill
-  for (int e = threadIdx.x; e < NR * kPlaneK; e += kMfmaThreads) {
-    const int k = e % kPlaneK, r = e / kPlaneK;
-    if (k >= X2 || r >= nrow || r % X1p >= X1)
-      for (int pl = 0; pl < 4; ++pl) plane[pl * NR * kPlaneK + e] = (_Float16)0.0f;
-  }
   __syncthreads();
   float bmx = 0.0f;
   for (int w = 0; w < NW; ++w) bmx = fmaxf(bmx, red[w]);
@@ -209,97 +229,130 @@ __global__ __launch_bounds__(kMfmaThreads) void k_gather_mfma(const cplx<float> 
   const float sc = ldexpf(1.0f, 14 - ex);  // scaled maximum in [2^13, 2^14)
   // 3. FP16 hi/lo planes
 #pragma unroll
-  for (int u = 0; u < kBoxPerThread; ++u) {
-    const int e = threadIdx.x + u * kMfmaThreads;
-    if (e < X0 * X1 * X2) {
-      const int i2 = e % X2, r = e / X2, i1 = r % X1, i0 = r / X1;
-      const int o = (i0 * X1p + i1) * kPlaneK + i2;
-      const float vr = v[u].re * sc, vi = v[u].im * sc;
-      const _Float16 rh = (_Float16)vr, ih = (_Float16)vi;
-      plane[o] = rh;
-      plane[NR * kPlaneK + o] = (_Float16)(vr - (float)rh);
-      plane[2 * NR * kPlaneK + o] = ih;
-      plane[3 * NR * kPlaneK + o] = (_Float16)(vi - (float)ih);
+  for (int u = 0; u < Sh::KB; ++u) {
+    const int e = threadIdx.x + u * NT;
+    if (e < Sh::items) {
+      const int o = (e / (kPlaneK / 2)) * kPlaneK + 2 * (e % (kPlaneK / 2));
+      const sgl_float2 re = {v[u][0].re * sc, v[u][1].re * sc}, im = {v[u][0].im * sc, v[u][1].im * sc};
+      const sgl_half2 rh = __builtin_convertvector(re, sgl_half2), ih = __builtin_convertvector(im, sgl_half2);
+      const sgl_half2 rl = __builtin_convertvector(sgl_float2{re[0] - (float)rh[0], re[1] - (float)rh[1]}, sgl_half2);
+      const sgl_half2 il = __builtin_convertvector(sgl_float2{im[0] - (float)ih[0], im[1] - (float)ih[1]}, sgl_half2);
+      *(sgl_half2 *)(plane + o) = rh;
+      *(sgl_half2 *)(plane + PS + o) = rl;
+      *(sgl_half2 *)(plane + 2 * PS + o) = ih;
+      *(sgl_half2 *)(plane + 3 * PS + o) = il;
     }
   }
   __syncthreads();
 
-  // 4. every wave walks its own batches of 16 points
+  // 4. every wave takes passes of 32 points (two groups of 16)
   const int pl = lane & 15, h = lane >> 4;
-  float *tab = wtab + (size_t)(wave * 16 + pl) * kTabStride;
+  const int ha = h < 3 ? h : 2;  // lanes h = 3 meet the zero K rows 24..31 of B; any finite A serves
   const float kexp = -inv2lam * 1.4426950408889634f;
-  for (int b0 = wave * 16; b0 < count; b0 += NW * 16) {
-    const int k = start + b0 + pl;
-    const bool valid = b0 + pl < count;
-    PointRec<float> pr;
-    pr.frac[0] = pr.frac[1] = pr.frac[2] = 0.0f;
-    pr.cell = 0;
-    int o0 = 1 << 20, o1 = 1 << 20, o2 = 1 << 20;  // outside every box when invalid
-    if (valid) {
-      pr = pts[k];
-      o0 = cell0(pr.cell) - c0 * g.L[0];
-      o1 = cell1(pr.cell) - c1 * 8;
-      o2 = cell2(pr.cell) - c2 * 8;
-    }
-    // box-shifted w0 / w1 of this lane's point (the four lanes of a point split the work)
-    for (int i = h; i < kWaveTab; i += 4) {
-      const int t0 = i - o0, t1 = i - o1;
-      const float d0 = pr.frac[0] + (float)(q - 1 - t0), d1 = pr.frac[1] + (float)(q - 1 - t1);
-      tab[i] = ((unsigned)t0 < (unsigned)Q2) ? exp2f(d0 * d0 * kexp) : 0.0f;
-      tab[kWaveTab + i] = ((unsigned)t1 < (unsigned)Q2) ? exp2f(d1 * d1 * kexp) : 0.0f;
-    }
-    // B fragment: w2 of this lane's point at i2 = 8h + j (zero for h = 3)
-    sgl_half8 bh, bl;
+  const float inv = 1.0f / sc;
+  const int npass = (count + 31) / 32;
+  float *tb0 = wtab + (size_t)(wave * 32 + pl) * S, *tb1 = tb0 + 16 * S;
+  for (int ps = wave; ps < npass; ps += NW) {
+    sgl_half8 bh[2], bl[2];
+    int kk[2], o0[2];
+    float d0[2];  // w0 at i0 is gauss(d0 - i0) inside the window
+    bool valid[2];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int t2 = 8 * h + j - o2;
-      const float d2 = pr.frac[2] + (float)(q - 1 - t2);
-      const float w = (h < 3 && (unsigned)t2 < (unsigned)Q2) ? exp2f(d2 * d2 * kexp) : 0.0f;
-      const _Float16 wh = (_Float16)w;
-      bh[j] = wh;
-      bl[j] = (_Float16)(w - (float)wh);
+    for (int gi = 0; gi < 2; ++gi) {
+      const int idx = ps * 32 + gi * 16 + pl;
+      valid[gi] = idx < count;
+      kk[gi] = start + idx;
+      float fr0 = 0.0f, fr1 = 0.0f, fr2 = 0.0f;
+      int o1 = 1 << 20, o2 = 1 << 20;  // outside every box when invalid
+      o0[gi] = 1 << 20;
+      if (valid[gi]) {
+        const PointRec<float> pr = pts[kk[gi]];
+        fr0 = pr.frac[0];
+        fr1 = pr.frac[1];
+        fr2 = pr.frac[2];
+        o0[gi] = cell0(pr.cell) - c0 * 8;
+        o1 = cell1(pr.cell) - c1 * 8;
+        o2 = cell2(pr.cell) - c2 * 8;
+      }
+      d0[gi] = fr0 + (float)(q - 1 + o0[gi]);
+      float *tb = gi ? tb1 : tb0;
+#pragma unroll
+      for (int i1 = 0; i1 < X1p; i1 += 4) {
+        const int t = i1 + h - o1;
+        const float d = fr1 + (float)(q - 1 - t);
+        tb[i1 + h] = ((unsigned)t < (unsigned)Q2) ? __builtin_amdgcn_exp2f(d * d * kexp) : 0.0f;
+      }
+      float w[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int t = 8 * h + j - o2;
+        const float d = fr2 + (float)(q - 1 - t);
+        w[j] = (h < 3 && (unsigned)t < (unsigned)Q2) ? __builtin_amdgcn_exp2f(d * d * kexp) : 0.0f;
+      }
+#pragma unroll
+      for (int j = 0; j < 8; j += 2) {
+        const sgl_half2 hh = __builtin_convertvector(sgl_float2{w[j], w[j + 1]}, sgl_half2);
+        const sgl_half2 ll =
+            __builtin_convertvector(sgl_float2{w[j] - (float)hh[0], w[j + 1] - (float)hh[1]}, sgl_half2);
+        bh[gi][j] = hh[0];
+        bh[gi][j + 1] = hh[1];
+        bl[gi][j] = ll[0];
+        bl[gi][j + 1] = ll[1];
+      }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    float ar = 0.0f, ai = 0.0f;
-    for (int rb = 0; rb < nrb; ++rb) {
-      const int arow = rb * 16 + pl;
-      sgl_half8 a0 = {}, a1 = {}, a2 = {}, a3 = {};
-      if (h < 3) {
-        const size_t off = (size_t)arow * kPlaneK + 8 * h;
-        a0 = *(const sgl_half8 *)(plane + off);
-        a1 = *(const sgl_half8 *)(plane + NR * kPlaneK + off);
-        a2 = *(const sgl_half8 *)(plane + 2 * NR * kPlaneK + off);
-        a3 = *(const sgl_half8 *)(plane + 3 * NR * kPlaneK + off);
-      }
+    float ar[2] = {0.0f, 0.0f}, ai[2] = {0.0f, 0.0f};
+#pragma unroll UR
+    for (int rb = 0; rb < Sh::nrb; ++rb) {
+      const _Float16 *ap = plane + (rb * 16 + pl) * kPlaneK + 8 * ha;
+      const sgl_half8 a0 = *(const sgl_half8 *)ap;
+      const sgl_half8 a1 = *(const sgl_half8 *)(ap + PS);
+      const sgl_half8 a2 = *(const sgl_half8 *)(ap + 2 * PS);
+      const sgl_half8 a3 = *(const sgl_half8 *)(ap + 3 * PS);
       // rows 4h .. 4h+3 of the block: one i0, i1 = i1b .. i1b+3
       const int r4 = rb * 16 + 4 * h;
-      const int i0 = r4 / X1p, i1b = r4 - i0 * X1p;
-      const float w0 = (r4 < nrow) ? tab[i0] : 0.0f;
-      const sgl_float4 w1 = *(const sgl_float4 *)(tab + kWaveTab + i1b);
-      float cw[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) cw[j] = w0 * w1[j];
-      sgl_float4 dr = {0, 0, 0, 0}, di = {0, 0, 0, 0};
-      dr = __builtin_amdgcn_mfma_f32_16x16x32_f16(a0, bh, dr, 0, 0, 0);
-      di = __builtin_amdgcn_mfma_f32_16x16x32_f16(a2, bh, di, 0, 0, 0);
-      dr = __builtin_amdgcn_mfma_f32_16x16x32_f16(a0, bl, dr, 0, 0, 0);
-      di = __builtin_amdgcn_mfma_f32_16x16x32_f16(a2, bl, di, 0, 0, 0);
-      dr = __builtin_amdgcn_mfma_f32_16x16x32_f16(a1, bh, dr, 0, 0, 0);
-      di = __builtin_amdgcn_mfma_f32_16x16x32_f16(a3, bh, di, 0, 0, 0);
+      const int i0 = r4 / X1p, i1b = r4 - (r4 / X1p) * X1p;
+      // four independent accumulation chains, interleaved
+      sgl_float4 dr0 = {0, 0, 0, 0}, di0 = {0, 0, 0, 0}, dr1 = {0, 0, 0, 0}, di1 = {0, 0, 0, 0};
+      dr0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(a0, bh[0], dr0, 0, 0, 0);
+      di0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(a2, bh[0], di0, 0, 0, 0);
+      dr1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(a0, bh[1], dr1, 0, 0, 0);
+      di1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(a2, bh[1], di1, 0, 0, 0);
+      dr0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(a0, bl[0], dr0, 0, 0, 0);
+      di0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(a2, bl[0], di0, 0, 0, 0);
+      dr1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(a0, bl[1], dr1, 0, 0, 0);
+      di1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(a2, bl[1], di1, 0, 0, 0);
+      dr0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(a1, bh[0], dr0, 0, 0, 0);
+      di0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(a3, bh[0], di0, 0, 0, 0);
+      dr1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(a1, bh[1], dr1, 0, 0, 0);
+      di1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(a3, bh[1], di1, 0, 0, 0);
+      // w0 of the lane's row group (zero outside the window, e.g. rows past the box)
+      const int t00 = i0 - o0[0], t01 = i0 - o0[1];
+      const float e0 = d0[0] - (float)i0, e1 = d0[1] - (float)i0;
+      const float w00 = ((unsigned)t00 < (unsigned)Q2) ? __builtin_amdgcn_exp2f(e0 * e0 * kexp) : 0.0f;
+      const float w01 = ((unsigned)t01 < (unsigned)Q2) ? __builtin_amdgcn_exp2f(e1 * e1 * kexp) : 0.0f;
+      const sgl_float4 w10 = *(const sgl_float4 *)(tb0 + i1b);
+      const sgl_float4 w11 = *(const sgl_float4 *)(tb1 + i1b);
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        ar += cw[j] * dr[j];
-        ai += cw[j] * di[j];
+        const float cw0 = w00 * w10[j], cw1 = w01 * w11[j];
+        ar[0] += cw0 * dr0[j];
+        ai[0] += cw0 * di0[j];
+        ar[1] += cw1 * dr1[j];
+        ai[1] += cw1 * di1[j];
       }
     }
-    // the four lanes of a point hold disjoint rows: sum them
-    ar += __shfl_xor(ar, 16);
-    ai += __shfl_xor(ai, 16);
-    ar += __shfl_xor(ar, 32);
-    ai += __shfl_xor(ai, 32);
-    if (valid && h == 0) f[perm[k]] = cplx<float>{ar / sc, ai / sc};
+#pragma unroll
+    for (int gi = 0; gi < 2; ++gi) {
+      // the four lanes of a point hold disjoint rows: sum them
+      ar[gi] += __shfl_xor(ar[gi], 16);
+      ai[gi] += __shfl_xor(ai[gi], 16);
+      ar[gi] += __shfl_xor(ar[gi], 32);
+      ai[gi] += __shfl_xor(ai[gi], 32);
+      if (valid[gi] && h == 0) f[perm[kk[gi]]] = cplx<float>{ar[gi] * inv, ai[gi] * inv};
+    }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
   }
@@ -652,8 +705,6 @@ constexpr int kTS = kSB + 4;         // floats per weight-table row (conflict-fr
 constexpr int kBS = kSB + 8;         // halves per B-plane column (conflict-free b128 reads)
 constexpr int kNoExp = -100;         // running exponent before the first nonzero sample
 
-typedef float sgl_float2 __attribute__((ext_vector_type(2)));
-typedef _Float16 sgl_half2 __attribute__((ext_vector_type(2)));
 
 // FP16 hi + lo parts of eight FP32 values (hi rounded to nearest, lo = the
 // rounded remainder)
@@ -1038,13 +1089,9 @@ hipError_t gather_q(const Plan &p, const void *grid, void *f) {
   const Geom g = make_geom(p);
   const R inv2lam = (R)(1.0 / (2.0 * p.lambda));
   if constexpr (std::is_same<R, float>::value && Q2 <= 16) {
-    if (p.gather_mode == 0 && p.mfma && p.L[1] == 8 && p.L[2] == 8 &&
-        p.X[0] * p.X[1] * p.X[2] <= kMfmaThreads * kBoxPerThread && p.X[0] <= kWaveTab) {
-      const int nrow = p.X[0] * ((p.X[1] + 3) & ~3);
-      const size_t lds = (size_t)4 * ((nrow + 15) / 16 * 16) * kPlaneK * sizeof(_Float16) +
-                         (size_t)(kMfmaThreads / 64) * 16 * kTabStride * sizeof(float);
+    if (p.gather_mode == 0 && p.mfma && p.L[0] == 8 && p.L[1] == 8 && p.L[2] == 8) {
       // gfx950 grants up to 160 KB of LDS per workgroup without an opt-in
-      k_gather_mfma<Q2><<<(unsigned)p.nchunks, kMfmaThreads, lds, p.stream>>>(
+      k_gather_mfma<Q2><<<(unsigned)p.nchunks, GatherShape<Q2>::threads, GatherShape<Q2>::lds, p.stream>>>(
           (const cplx<float> *)grid, (const PointRec<float> *)p.pts, p.perm, p.chunks, g, (float)inv2lam,
           (cplx<float> *)f);
       return hipGetLastError();
