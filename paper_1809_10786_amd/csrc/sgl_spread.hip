@@ -1140,9 +1140,63 @@ hipError_t scatter_q(const Plan &p, const void *f, void *grid) {
   return hipGetLastError();
 }
 
+// Fold for tiles of 8^3 cells when dimensions 0 and 1 are pruned and
+// dimension 2 is the full period N2 = 8 T2 >= X: the box of tile c starts at
+// stored index 8c in dimensions 0 and 1 and at 8c - q + 1 (mod N2) in
+// dimension 2, so stored cell s lies in the boxes of the tiles
+// floor(s'/8) - k, k = 0, 1, 2, at box index (s' mod 8) + 8k < X (s' = s, or
+// s + q - 1 mod N2 in dimension 2).  One thread per stored cell sums those
+// boxes (all chunks of each tile, in order) in double precision; a wave covers
+// 64 consecutive cells of one row, whose box entries are contiguous.
+template <class R>
+__global__ __launch_bounds__(256) void k_fold_tiles8(const cplx<R> *__restrict__ staging,
+                                                     const int32_t *__restrict__ tile_chunk, Geom g,
+                                                     cplx<double> *__restrict__ grid) {
+  const int64_t cell = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (cell >= (int64_t)g.E[0] * g.E[1] * g.E[2]) return;
+  const int X = g.X[0];
+  const size_t ncell = (size_t)X * X * X;
+  const int s2 = (int)(cell % g.E[2]);
+  const int r = (int)(cell / g.E[2]);
+  const int s1 = r % g.E[1], s0 = r / g.E[1];
+  int sp2 = s2 + g.q - 1;
+  if (sp2 >= g.N[2]) sp2 -= g.N[2];
+  double ar = 0.0, ai = 0.0;
+  for (int k0 = 0; k0 < 3; ++k0) {
+    const int c0 = (s0 >> 3) - k0, i0 = (s0 & 7) + 8 * k0;
+    if (c0 < 0 || c0 >= g.T[0] || i0 >= X) continue;
+    for (int k1 = 0; k1 < 3; ++k1) {
+      const int c1 = (s1 >> 3) - k1, i1 = (s1 & 7) + 8 * k1;
+      if (c1 < 0 || c1 >= g.T[1] || i1 >= X) continue;
+      for (int k2 = 0; k2 < 3; ++k2) {
+        const int i2 = (sp2 & 7) + 8 * k2;
+        if (i2 >= X) continue;
+        int c2 = (sp2 >> 3) - k2;
+        if (c2 < 0) c2 += g.T[2];
+        const int tile = (c0 * g.T[1] + c1) * g.T[2] + c2;
+        const int ch0 = tile_chunk[tile], ch1 = tile_chunk[tile + 1];
+        const size_t off = ((size_t)i0 * X + i1) * X + i2;
+        for (int ch = ch0; ch < ch1; ++ch) {
+          const cplx<R> v = staging[(size_t)ch * ncell + off];
+          ar += v.re;
+          ai += v.im;
+        }
+      }
+    }
+  }
+  grid[cell] = cplx<double>{ar, ai};
+}
+
 template <class R>
 hipError_t fold_r(const Plan &p, void *grid) {
   const Geom g = make_geom(p);
+  if (p.L[0] == 8 && p.L[1] == 8 && p.L[2] == 8 && p.X[0] == p.X[1] && p.X[1] == p.X[2] && p.X[0] <= 24 &&
+      p.pruned[0] && p.pruned[1] && !p.pruned[2] && p.N[2] == 8 * p.T[2] && p.E[2] == p.N[2] && p.X[2] <= p.N[2]) {
+    const int64_t cells = (int64_t)p.E[0] * p.E[1] * p.E[2];
+    k_fold_tiles8<R><<<(unsigned)((cells + 255) / 256), 256, 0, p.stream>>>((const cplx<R> *)p.staging, p.tile_chunk,
+                                                                           g, (cplx<double> *)grid);
+    return hipGetLastError();
+  }
   const int F0 = p.F[0], F1 = p.F[1], F2 = p.F[2];
   const int64_t nb = (int64_t)((p.E[0] + F0 - 1) / F0) * ((p.E[1] + F1 - 1) / F1) * ((p.E[2] + F2 - 1) / F2);
   k_fold_staging<R><<<(unsigned)nb, 256, 0, p.stream>>>((const cplx<R> *)p.staging, p.tile_chunk, g, F0, F1, F2,
