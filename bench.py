@@ -24,6 +24,7 @@ METRIC = "scattered points/s fwd+adj at B=64, M=4e6, rel err≤1e-5; frac of HBM
 
 # MI355X published peaks
 HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_F16_TFLOPS = 2500.0  # dense FP16 matrix cores
 # FP32 vector FMA issue rate without packed math: 256 CU x 4 SIMD x 16 lanes x
 # 2 flop x 2.4 GHz (the build disables packed FP32 instructions).
 ALU_PEAK_F32_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
@@ -114,9 +115,20 @@ def accuracy(B, plan, pts_used, fh_used, f_gpu, y, prec, m, torch, cdt):
 
 # ---------------------------------------------------------------- profiles
 
-STAGE_KERNEL = {"gather": "k_gather_tiled", "scatter": "k_spread_rows", "fold": "k_fold_staging"}
+STAGE_KERNEL_VALU = {"gather": "k_gather_tiled", "scatter": "k_spread_rows", "fold": "k_fold_staging"}
+STAGE_KERNEL_MFMA = {"gather": "k_gather_mfma", "scatter": "k_spread_mfma", "fold": "k_fold_tiles8"}
+STAGE_KERNEL = dict(STAGE_KERNEL_MFMA)  # kernels of the benchmarked FP32 workload
 KERNEL_SOURCE = {"k_gather_tiled": "sgl_spread.hip", "k_spread_rows": "sgl_spread.hip",
-                 "k_fold_staging": "sgl_spread.hip", "k_fft": "sgl_fft.hip"}
+                 "k_fold_staging": "sgl_spread.hip", "k_gather_mfma": "sgl_spread.hip",
+                 "k_spread_mfma": "sgl_spread.hip", "k_fold_tiles8": "sgl_spread.hip", "k_fft": "sgl_fft.hip"}
+
+
+def stage_kernels(info):
+    """Kernel that runs each gather/scatter/fold stage of a plan (plan info)."""
+    k = dict(STAGE_KERNEL_MFMA if info["gather_mode"] == 2 else STAGE_KERNEL_VALU)
+    if (info["L0"], info["L1"], info["L2"]) != (8, 8, 8):
+        k["fold"] = "k_fold_staging"
+    return k
 
 
 def source_digest(kernel):
@@ -262,13 +274,20 @@ def main():
     avg = {k: v[0] / v[1] for k, v in stages.items()}
     dom = max(avg, key=avg.get)
     fb = fft_bytes(info, B, cb)
+    kern = stage_kernels(info)
     if dom in ("gather", "scatter"):
+        # algorithmic flops: (2q)^3 complex-by-real multiply-adds per point
         flops = spread_flops(q) * M
-        peak = ALU_PEAK_F32_TFLOPS if prec == "f32" else ALU_PEAK_F64_TFLOPS
         achieved = flops / (avg[dom] * 1e-3) / 1e12
-        roof = {"kernel": STAGE_KERNEL.get(dom, dom), "bound": "alu", "achieved": achieved, "peak": peak,
+        if info["gather_mode"] == 2:
+            # the contraction runs on the FP16 matrix cores (hi/lo split operands)
+            bound, peak = "mfma", MFMA_PEAK_F16_TFLOPS
+        else:
+            bound, peak = "alu", ALU_PEAK_F32_TFLOPS if prec == "f32" else ALU_PEAK_F64_TFLOPS
+        roof = {"kernel": kern[dom], "bound": bound, "achieved": achieved, "peak": peak,
                 "unit": "TFLOP/s", "frac": achieved / peak,
-                "traffic": profiled_traffic(a.workload, STAGE_KERNEL.get(dom, dom))}
+                "frac_of_fp32_vector_peak": achieved / ALU_PEAK_F32_TFLOPS,
+                "traffic": profiled_traffic(a.workload, kern[dom])}
     else:
         byts = fb.get(dom, 0)
         achieved = byts / (avg[dom] * 1e-3) / 1e9

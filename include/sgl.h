@@ -127,7 +127,8 @@ sgl_status sgl_plan_rho(sgl_plan_t plan, double *rho);
 /* Informational: number of points, FFT grid sigma*n, stored (pruned) grid
  * extents, gather tile edges, and bytes of device workspace.  info must
  * hold 12 int64 values: {M, N0, N1, N2, E0, E1, E2, L0, L1, L2, bytes,
- * gather_mode (0 = LDS tiles, 1 = direct)}. */
+ * gather_mode (0 = LDS tiles, 1 = direct, 2 = LDS tiles with the FP16
+ * hi/lo matrix-core gather and spread of FP32 plans)}. */
 sgl_status sgl_plan_info(sgl_plan_t plan, int64_t info[12]);
 
 /* Stages timed by the optional per-stage profiler (forward: radial and polar

@@ -154,6 +154,7 @@ sgl_status setup_geometry(Plan &p) {
     p.ntiles *= p.T[j];
   }
   if ((uint64_t)p.ntiles * p.L[0] * p.L[1] * p.L[2] >= (1ull << 32)) return SGL_E_UNSUPPORTED;
+  p.mfma = (p.prec == SGL_F32 && p.gather_mode == 0 && p.q <= 8 && p.L[0] == 8 && p.L[1] == 8 && p.L[2] == 8);
   // scatter blocks over stored cells
   // 16^3 cells (FP32) or 16 x 16 x 8 (FP64): 32 KB of LDS accumulators
   const int lo_edge[3] = {16, 16, p.prec == SGL_F64 ? 8 : 16};
@@ -505,7 +506,7 @@ sgl_status sgl_plan_info(sgl_plan_t plan, int64_t info[12]) {
   if (check_plan(plan) != SGL_OK || !info) return SGL_E_INVAL;
   const Plan &p = plan->p;
   const int64_t v[12] = {p.M, p.N[0], p.N[1], p.N[2], p.E[0], p.E[1], p.E[2],
-                         p.L[0], p.L[1], p.L[2], (int64_t)p.bytes, p.gather_mode};
+                         p.L[0], p.L[1], p.L[2], (int64_t)p.bytes, p.mfma ? 2 : p.gather_mode};
   std::memcpy(info, v, sizeof(v));
   return SGL_OK;
 }

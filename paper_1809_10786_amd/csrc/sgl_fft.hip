@@ -216,10 +216,201 @@ __global__ __launch_bounds__(256) void k_fft(const cplx<Ri> *__restrict__ in, cp
   }
 }
 
+// ---------------------------------------------------------------- power-of-two lengths
+
+// LDS row stride (elements per position) for W lines: contiguous lines
+// (inner == 1) are padded by one element so that the rows of one line land
+// in different banks; strided lines are read and written row by row and need
+// no padding.
+template <int W, bool STRIDED>
+constexpr int p2_stride() {
+  return STRIDED ? W : W + 1;
+}
+
+// Lines per workgroup for length L = 2^LOG2L and element type R: as many as
+// keep the line buffer and the twiddles within 78 KB (two workgroups per
+// compute unit), at most 16 (16 FP32 or 8 FP64 lines fill a 128-byte row of a
+// strided pass).
+template <class R, int LOG2L, bool STRIDED>
+constexpr int p2_lines() {
+  int w = 16;
+  while (w > 1 && ((size_t)(1 << LOG2L) * (STRIDED ? w : w + 1) + (1 << LOG2L)) * sizeof(cplx<R>) > 78 * 1024)
+    w /= 2;
+  return w;
+}
+
+template <class R, int LOG2L, bool STRIDED>
+constexpr int p2_threads() {
+  return ((1 << LOG2L) / 8) * p2_lines<R, LOG2L, STRIDED>() >= 1024 ? 512 : 256;
+}
+
+// One in-place Stockham stage of radix RAD after NS points (NS = product of
+// the radices already applied): every thread reads its butterflies' inputs
+// into registers, the group synchronises, and the outputs are written back
+// in autosort order.  LDS element (position, line) sits at position * SW + line.
+template <class R, int NT, int L, int W, int SW, int RAD, int NS>
+__device__ inline void p2_stage(cplx<R> *buf, const cplx<R> *tw, int sign) {
+  constexpr int NB = (L / RAD) * W;
+  constexpr int PER = (NB + NT - 1) / NT;
+  cplx<R> v[PER][RAD];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int b = threadIdx.x + u * NT;
+    if (NB % NT == 0 || b < NB) {
+      const int w = b % W, j = b / W;
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) v[u][r] = buf[(j + r * (L / RAD)) * SW + w];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int b = threadIdx.x + u * NT;
+    if (NB % NT == 0 || b < NB) {
+      const int w = b % W, j = b / W, k = j % NS;
+      if (NS > 1) {
+#pragma unroll
+        for (int r = 1; r < RAD; ++r) {
+          cplx<R> t = tw[r * k * (L / (NS * RAD))];
+          if (sign < 0) t.im = -t.im;
+          v[u][r] = cmul(v[u][r], t);
+        }
+      }
+      Dft<R, RAD>::run(v[u], sign);
+      const int d = (j / NS) * NS * RAD + k;
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) buf[(d + r * NS) * SW + w] = v[u][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <class R, int NT, int L, int W, int SW, int NS>
+__device__ inline void p2_stages8(cplx<R> *buf, const cplx<R> *tw, int sign) {
+  if constexpr (NS < L) {
+    p2_stage<R, NT, L, W, SW, 8, NS>(buf, tw, sign);
+    p2_stages8<R, NT, L, W, SW, NS * 8>(buf, tw, sign);
+  }
+}
+
+// The pass of k_fft for L = 2^LOG2L with compile-time geometry; STRIDED
+// selects the [outer][axis][inner > 1] view (lines are adjacent inner
+// indices), otherwise every line is contiguous.
+template <class Ri, class R, int LOG2L, bool STRIDED>
+__global__ __launch_bounds__((p2_threads<R, LOG2L, STRIDED>())) void k_fft_p2(
+    const cplx<Ri> *__restrict__ in, cplx<R> *__restrict__ out, FftPass fp, const cplx<double> *__restrict__ tw64,
+    const double *__restrict__ dc, int dcmode, int n0, int n1) {
+  constexpr int L = 1 << LOG2L;
+  constexpr int W = p2_lines<R, LOG2L, STRIDED>();
+  constexpr int SW = p2_stride<W, STRIDED>();
+  constexpr int NT = p2_threads<R, LOG2L, STRIDED>();
+  constexpr int REM = LOG2L % 3 == 0 ? 1 : (LOG2L % 3 == 1 ? 2 : 4);
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  cplx<R> *buf = (cplx<R> *)smem;
+  cplx<R> *tw = buf + (size_t)L * SW;  // twiddles e^{2 pi i t / L} in the transform's precision
+  __shared__ double linefac[W];        // deconvolution factor of dimensions 0 and 1 per line
+  for (int t = threadIdx.x; t < L; t += NT) tw[t] = cplx<R>{(R)tw64[t].re, (R)tw64[t].im};
+
+  int o_base, ic_base;
+  if constexpr (STRIDED) {
+    const int gpo = (fp.inner + W - 1) / W;
+    o_base = blockIdx.x / gpo;
+    ic_base = (blockIdx.x % gpo) * W;
+  } else {
+    o_base = blockIdx.x * W;
+    ic_base = 0;
+  }
+  if (dcmode != 0 && threadIdx.x < W) {
+    const int o = STRIDED ? o_base : o_base + (int)threadIdx.x;
+    linefac[threadIdx.x] = o < fp.outer ? dc[o / n1] * dc[n0 + o % n1] : 0.0;
+  }
+  for (int e = threadIdx.x; e < L * SW; e += NT) buf[e] = cplx<R>{0, 0};
+  __syncthreads();
+
+  for (int e = threadIdx.x; e < fp.nin * W; e += NT) {
+    int i, w;
+    if constexpr (STRIDED) {
+      i = e / W;
+      w = e % W;
+    } else {
+      w = e / fp.nin;
+      i = e - w * fp.nin;
+    }
+    const int o = STRIDED ? o_base : o_base + w;
+    const int ic = STRIDED ? ic_base + w : 0;
+    if (o >= fp.outer || ic >= fp.inner) continue;
+    const cplx<Ri> vi = in[((size_t)o * fp.nin + i) * fp.inner + ic];
+    cplx<R> v = {(R)vi.re, (R)vi.im};
+    if (dcmode == 1) v = cscale(v, (R)(linefac[w] * dc[n0 + n1 + i]));
+    buf[((fp.in_off + i) & (L - 1)) * SW + w] = v;
+  }
+  __syncthreads();
+
+  if constexpr (REM > 1) p2_stage<R, NT, L, W, SW, REM, 1>(buf, tw, fp.sign);
+  p2_stages8<R, NT, L, W, SW, REM>(buf, tw, fp.sign);
+
+  for (int e = threadIdx.x; e < fp.nout * W; e += NT) {
+    int i, w;
+    if constexpr (STRIDED) {
+      i = e / W;
+      w = e % W;
+    } else {
+      w = e / fp.nout;
+      i = e - w * fp.nout;
+    }
+    const int o = STRIDED ? o_base : o_base + w;
+    const int ic = STRIDED ? ic_base + w : 0;
+    if (o >= fp.outer || ic >= fp.inner) continue;
+    cplx<R> v = buf[((fp.out_off + i) & (L - 1)) * SW + w];
+    if (dcmode == 2) v = cscale(v, (R)(linefac[w] * dc[n0 + n1 + i]));
+    out[((size_t)o * fp.nout + i) * fp.inner + ic] = v;
+  }
+}
+
+template <class Ri, class R, int LOG2L, bool STRIDED>
+hipError_t fft_p2s(const Plan &p, const FftPass &fp, const void *in, void *out, int tw_index, int dcmode) {
+  constexpr int W = p2_lines<R, LOG2L, STRIDED>();
+  constexpr int SW = p2_stride<W, STRIDED>();
+  constexpr int NT = p2_threads<R, LOG2L, STRIDED>();
+  const int groups = STRIDED ? fp.outer * ((fp.inner + W - 1) / W) : (fp.outer + W - 1) / W;
+  const size_t lds = ((size_t)(1 << LOG2L) * SW + (1 << LOG2L)) * sizeof(cplx<R>);
+  k_fft_p2<Ri, R, LOG2L, STRIDED><<<groups, NT, lds, p.stream>>>(
+      (const cplx<Ri> *)in, (cplx<R> *)out, fp, (const cplx<double> *)p.twiddle + p.tw_off[tw_index],
+      (const double *)p.deconv, dcmode, p.n[0], p.n[1]);
+  return hipGetLastError();
+}
+
+template <class Ri, class R, int LOG2L>
+hipError_t fft_p2(const Plan &p, const FftPass &fp, const void *in, void *out, int tw_index, int dcmode) {
+  if (fp.inner > 1) return fft_p2s<Ri, R, LOG2L, true>(p, fp, in, out, tw_index, dcmode);
+  return fft_p2s<Ri, R, LOG2L, false>(p, fp, in, out, tw_index, dcmode);
+}
+
+template <class Ri, class R>
+hipError_t fft_pow2(const Plan &p, const FftPass &fp, const void *in, void *out, int tw_index, int dcmode,
+                    bool *done) {
+  *done = true;
+  switch (fp.L) {
+    case 8: return fft_p2<Ri, R, 3>(p, fp, in, out, tw_index, dcmode);
+    case 16: return fft_p2<Ri, R, 4>(p, fp, in, out, tw_index, dcmode);
+    case 32: return fft_p2<Ri, R, 5>(p, fp, in, out, tw_index, dcmode);
+    case 64: return fft_p2<Ri, R, 6>(p, fp, in, out, tw_index, dcmode);
+    case 128: return fft_p2<Ri, R, 7>(p, fp, in, out, tw_index, dcmode);
+    case 256: return fft_p2<Ri, R, 8>(p, fp, in, out, tw_index, dcmode);
+    case 512: return fft_p2<Ri, R, 9>(p, fp, in, out, tw_index, dcmode);
+    case 1024: return fft_p2<Ri, R, 10>(p, fp, in, out, tw_index, dcmode);
+    case 2048: return fft_p2<Ri, R, 11>(p, fp, in, out, tw_index, dcmode);
+    default: *done = false; return hipSuccess;
+  }
+}
+
 }  // namespace
 
 template <class Ri, class R>
 hipError_t fft_typed(const Plan &p, const FftPass &fp, const void *in, void *out, int tw_index, int dcmode) {
+  bool done = false;
+  const hipError_t e = fft_pow2<Ri, R>(p, fp, in, out, tw_index, dcmode, &done);
+  if (done) return e;
   const int groups = fp.inner > 1 ? fp.outer * ((fp.inner + fp.W - 1) / fp.W) : (fp.outer + fp.W - 1) / fp.W;
   const size_t lds = (2 * (size_t)fp.L * fp.W + fp.L) * sizeof(cplx<R>);
   k_fft<Ri, R><<<groups, 256, lds, p.stream>>>((const cplx<Ri> *)in, (cplx<R> *)out, fp,

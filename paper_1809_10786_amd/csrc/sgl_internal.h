@@ -99,7 +99,7 @@ struct Plan {
   int L[3], T[3], NB[3], X[3];
   int64_t ntiles = 0;
   int gather_mode = 0;  // 0: LDS tiles, 1: direct from the grid
-  int mfma = 1;         // FP32: use the matrix-core gather when the tile shape allows
+  int mfma = 0;         // FP32, 8^3 tiles, q <= 8: matrix-core gather and spread
   // scatter output blocks over stored cells
   int Lo[3], To[3];
   int64_t nblocks = 0;

@@ -1089,7 +1089,7 @@ hipError_t gather_q(const Plan &p, const void *grid, void *f) {
   const Geom g = make_geom(p);
   const R inv2lam = (R)(1.0 / (2.0 * p.lambda));
   if constexpr (std::is_same<R, float>::value && Q2 <= 16) {
-    if (p.gather_mode == 0 && p.mfma && p.L[0] == 8 && p.L[1] == 8 && p.L[2] == 8) {
+    if (p.mfma) {
       // gfx950 grants up to 160 KB of LDS per workgroup without an opt-in
       k_gather_mfma<Q2><<<(unsigned)p.nchunks, GatherShape<Q2>::threads, GatherShape<Q2>::lds, p.stream>>>(
           (const cplx<float> *)grid, (const PointRec<float> *)p.pts, p.perm, p.chunks, g, (float)inv2lam,
@@ -1113,7 +1113,7 @@ hipError_t scatter_q(const Plan &p, const void *f, void *grid) {
   const Geom g = make_geom(p);
   const R inv2lam = (R)(1.0 / (2.0 * p.lambda));
   if constexpr (std::is_same<R, float>::value && Q2 <= 16) {
-    if (p.gather_mode == 0 && p.mfma && p.L[0] == 8 && p.L[1] == 8 && p.L[2] == 8) {
+    if (p.mfma) {
       k_spread_mfma<Q2><<<(unsigned)p.nchunks, kSpreadThreads, 0, p.stream>>>(
           (const cplx<float> *)f, (const PointRec<float> *)p.pts, p.perm, p.chunks, g, (float)inv2lam,
           (cplx<float> *)p.staging);
