@@ -171,8 +171,7 @@ sgl_status setup_geometry(Plan &p) {
     rows *= std::min<int64_t>(p.T[j], span / p.L[j] + 2 + (p.pruned[j] ? 0 : 2));
   }
   if (rows > 512) return SGL_E_UNSUPPORTED;
-  // FFT passes: [outer][axis][inner] views
-  // forward passes run in the plan's precision, adjoint passes in FP64
+  // FFT passes: [outer][axis][inner] views; every pass computes in FP64
   auto pass = [&](FftPass &fp, int j, int outer, int inner, int nin, int in_off, int nout, int out_off, int sign) {
     radices_of(p.N[j], fp);
     fp.outer = outer;
@@ -182,7 +181,7 @@ sgl_status setup_geometry(Plan &p) {
     fp.nout = nout;
     fp.out_off = out_off;
     fp.sign = sign;
-    fp.W = lines_per_group(p.N[j], sign > 0 ? cb : 16);
+    fp.W = lines_per_group(p.N[j], 16);
   };
   const int n0 = p.n[0], n1 = p.n[1], n2 = p.n[2];
   pass(p.passA, 2, n0 * n1, 1, n2, -n2 / 2, p.N[2], 0, +1);
@@ -229,9 +228,7 @@ sgl_status make_plan(Plan &p, const void *points) {
   } else {
     p.rho = maxr > 0.0 ? maxr : 1.0;
   }
-  // 2. geometry
-  sgl_status st = setup_geometry(p);
-  if (st != SGL_OK) return st;
+  // 2. geometry: set up by sgl_plan before any device work
   // 3. points: transform, key, sort into tiles
   const size_t M = (size_t)p.M;
   const size_t rec = p.prec == SGL_F64 ? sizeof(PointRec<double>) : sizeof(PointRec<float>);
@@ -273,7 +270,7 @@ sgl_status make_plan(Plan &p, const void *points) {
   if (p.gather_mode == 0)
     SGL_TRY(dev_alloc(p, &p.staging, (size_t)p.nchunks * p.X[0] * p.X[1] * p.X[2] * cbytes(p)));
   // 5. tables
-  st = p.prec == SGL_F64 ? build_tables<double>(p) : build_tables<float>(p);
+  const sgl_status st = p.prec == SGL_F64 ? build_tables<double>(p) : build_tables<float>(p);
   if (st != SGL_OK) return st;
   // 6. workspace
   const size_t cb = cbytes(p);
@@ -330,9 +327,10 @@ struct Stage {
     SGL_TRY(expr);               \
   } while (0)
 
-sgl_status conv_fwd(Plan &p, const void *fhat, void *eta) {
+// eta_f64: element type of the eta output (the products themselves run in FP64).
+sgl_status conv_fwd(Plan &p, const void *fhat, void *eta, int eta_f64) {
   SGL_STAGE(SGL_STAGE_CONV_RADIAL, launch_conv_radial(p, fhat));
-  SGL_STAGE(SGL_STAGE_CONV_POLAR, launch_conv_polar(p, eta));
+  SGL_STAGE(SGL_STAGE_CONV_POLAR, launch_conv_polar(p, eta, eta_f64));
   return SGL_OK;
 }
 
@@ -342,15 +340,23 @@ sgl_status conv_adj(Plan &p, const void *eta, int eta_f64, void *fhat) {
   return SGL_OK;
 }
 
-sgl_status nfft_fwd(Plan &p, const void *eta, void *f) {
+// eta_f64: element type of the eta input.  The three FFT passes run in FP64 in
+// both modes; the last one writes the grid in the plan's precision for the
+// gather.  An FP32 FFT would leave every grid value with an absolute error of
+// ~6e-8 of the largest ones, and the polynomial grows steeply towards r = rho:
+// points at small r, where |f| is far below its maximum, would lose their
+// relative accuracy.  Rounding the finished grid to FP32 keeps each value's
+// error relative to itself.
+sgl_status nfft_fwd(Plan &p, const void *eta, int eta_f64, void *f) {
   if (p.flags & SGL_FLAG_EXACT_NDFT) {
+    if (eta_f64 != (p.prec == SGL_F64)) return SGL_E_INVAL;
     SGL_STAGE(SGL_STAGE_NDFT, launch_ndft_forward(p, eta, f));
     return SGL_OK;
   }
-  const int f64 = p.prec == SGL_F64;
-  SGL_STAGE(SGL_STAGE_FFT_A, launch_fft_pass(p, p.passA, eta, p.bufX, 2, 1, f64, f64));
-  SGL_STAGE(SGL_STAGE_FFT_B, launch_fft_pass(p, p.passB, p.bufX, p.bufY, 1, 0, f64, f64));
-  SGL_STAGE(SGL_STAGE_FFT_C, launch_fft_pass(p, p.passC, p.bufY, p.bufX, 0, 0, f64, f64));
+  const int grid_f64 = p.prec == SGL_F64;
+  SGL_STAGE(SGL_STAGE_FFT_A, launch_fft_pass(p, p.passA, eta, p.bufX, 2, 1, eta_f64, 1));
+  SGL_STAGE(SGL_STAGE_FFT_B, launch_fft_pass(p, p.passB, p.bufX, p.bufY, 1, 0, 1, 1));
+  SGL_STAGE(SGL_STAGE_FFT_C, launch_fft_pass(p, p.passC, p.bufY, p.bufX, 0, 0, 1, grid_f64));
   SGL_STAGE(SGL_STAGE_GATHER, launch_gather(p, p.bufX, f));
   return SGL_OK;
 }
@@ -427,6 +433,12 @@ sgl_status sgl_plan(sgl_plan_t *out, const sgl_params *prm, int64_t M, const voi
   p.M = M;
   p.rho = prm->rho > 0 ? prm->rho : 0.0;
   p.stream = (hipStream_t)hip_stream;
+  // host-only geometry checks (FFT lengths, tile tables) come before any device call
+  const sgl_status sg = setup_geometry(p);
+  if (sg != SGL_OK) {
+    delete h;
+    return sg;
+  }
   if (hipGetDevice(&p.device) != hipSuccess) {
     delete h;
     return SGL_E_DEVICE;
@@ -447,7 +459,7 @@ sgl_status sgl_conv_forward(sgl_plan_t plan, const void *fhat_dev, void *eta_dev
   Plan &p = plan->p;
   const size_t cb = cbytes(p);
   if (overlaps(fhat_dev, sgl_num_coeffs(p.B) * cb, eta_dev, (size_t)p.n[0] * p.n[1] * p.n[2] * cb)) return SGL_E_INVAL;
-  return conv_fwd(p, fhat_dev, eta_dev);
+  return conv_fwd(p, fhat_dev, eta_dev, p.prec == SGL_F64);
 }
 
 sgl_status sgl_conv_adjoint(sgl_plan_t plan, const void *eta_dev, void *fhat_dev) {
@@ -463,7 +475,7 @@ sgl_status sgl_nfft_forward(sgl_plan_t plan, const void *eta_dev, void *f_dev) {
   Plan &p = plan->p;
   const size_t cb = cbytes(p);
   if (overlaps(eta_dev, (size_t)p.n[0] * p.n[1] * p.n[2] * cb, f_dev, (size_t)p.M * cb)) return SGL_E_INVAL;
-  return nfft_fwd(p, eta_dev, f_dev);
+  return nfft_fwd(p, eta_dev, p.prec == SGL_F64, f_dev);
 }
 
 sgl_status sgl_nfft_adjoint(sgl_plan_t plan, const void *f_dev, void *eta_dev) {
@@ -479,9 +491,11 @@ sgl_status sgl_forward(sgl_plan_t plan, const void *fhat_dev, void *f_dev) {
   Plan &p = plan->p;
   const size_t cb = cbytes(p);
   if (overlaps(fhat_dev, sgl_num_coeffs(p.B) * cb, f_dev, (size_t)p.M * cb)) return SGL_E_INVAL;
-  const sgl_status st = conv_fwd(p, fhat_dev, p.eta);
+  // the fast path hands FP64 eta from the conversion to the FFT in both modes
+  const int eta_f64 = (p.flags & SGL_FLAG_EXACT_NDFT) ? (p.prec == SGL_F64) : 1;
+  const sgl_status st = conv_fwd(p, fhat_dev, p.eta, eta_f64);
   if (st != SGL_OK) return st;
-  return nfft_fwd(p, p.eta, f_dev);
+  return nfft_fwd(p, p.eta, eta_f64, f_dev);
 }
 
 sgl_status sgl_adjoint(sgl_plan_t plan, const void *f_dev, void *fhat_dev) {

@@ -253,8 +253,8 @@ hipError_t radial_adj(const Plan &p, void *fhat) {
 hipError_t launch_conv_radial(const Plan &p, const void *fhat) {
   return p.prec == SGL_F64 ? radial<double>(p, fhat) : radial<float>(p, fhat);
 }
-hipError_t launch_conv_polar(const Plan &p, void *eta) {
-  return p.prec == SGL_F64 ? polar<double>(p, eta) : polar<float>(p, eta);
+hipError_t launch_conv_polar(const Plan &p, void *eta, int eta_f64) {
+  return eta_f64 ? polar<double>(p, eta) : polar<float>(p, eta);
 }
 hipError_t launch_conv_polar_adj(const Plan &p, const void *eta, int eta_f64) {
   return eta_f64 ? polar_adj<double>(p, eta) : polar_adj<float>(p, eta);

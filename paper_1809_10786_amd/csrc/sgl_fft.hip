@@ -135,11 +135,14 @@ __device__ inline int wrap(int i, int L) {
 
 // dcmode: 0 none; 1 multiply input row i of line o by dc0[o / n1] dc1[o % n1]
 // dc2[i]; 2 the same on output rows (pass A of the forward / adjoint).
-// Ri: element type read, R: type of the transform and of the output.
-template <class Ri, class R>
-__global__ __launch_bounds__(256) void k_fft(const cplx<Ri> *__restrict__ in, cplx<R> *__restrict__ out, FftPass fp,
+// Ri: element type read, Ro: element type written; the transform itself runs
+// in FP64 (the grid's values span many orders of magnitude towards r = rho and
+// an FP32 transform leaves errors of the size of the largest ones everywhere).
+template <class Ri, class Ro>
+__global__ __launch_bounds__(256) void k_fft(const cplx<Ri> *__restrict__ in, cplx<Ro> *__restrict__ out, FftPass fp,
                                              const cplx<double> *__restrict__ tw64, const double *__restrict__ dc,
                                              int dcmode, int n0, int n1) {
+  using R = double;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int L = fp.L, W = fp.W;
   cplx<R> *buf0 = (cplx<R> *)smem;
@@ -212,7 +215,7 @@ __global__ __launch_bounds__(256) void k_fft(const cplx<Ri> *__restrict__ in, cp
     if (o >= fp.outer || ic >= fp.inner) continue;
     cplx<R> v = src[wrap(fp.out_off + i, L) * W + w];
     if (dcmode == 2) v = cscale(v, (R)(dc[o / n1] * dc[n0 + o % n1] * dc[n0 + n1 + i]));
-    out[((size_t)o * fp.nout + i) * fp.inner + ic] = v;
+    out[((size_t)o * fp.nout + i) * fp.inner + ic] = cplx<Ro>{(Ro)v.re, (Ro)v.im};
   }
 }
 
@@ -296,10 +299,11 @@ __device__ inline void p2_stages8(cplx<R> *buf, const cplx<R> *tw, int sign) {
 // The pass of k_fft for L = 2^LOG2L with compile-time geometry; STRIDED
 // selects the [outer][axis][inner > 1] view (lines are adjacent inner
 // indices), otherwise every line is contiguous.
-template <class Ri, class R, int LOG2L, bool STRIDED>
-__global__ __launch_bounds__((p2_threads<R, LOG2L, STRIDED>())) void k_fft_p2(
-    const cplx<Ri> *__restrict__ in, cplx<R> *__restrict__ out, FftPass fp, const cplx<double> *__restrict__ tw64,
+template <class Ri, class Ro, int LOG2L, bool STRIDED>
+__global__ __launch_bounds__((p2_threads<double, LOG2L, STRIDED>())) void k_fft_p2(
+    const cplx<Ri> *__restrict__ in, cplx<Ro> *__restrict__ out, FftPass fp, const cplx<double> *__restrict__ tw64,
     const double *__restrict__ dc, int dcmode, int n0, int n1) {
+  using R = double;  // the transform runs in FP64 (see k_fft)
   constexpr int L = 1 << LOG2L;
   constexpr int W = p2_lines<R, LOG2L, STRIDED>();
   constexpr int SW = p2_stride<W, STRIDED>();
@@ -363,62 +367,63 @@ __global__ __launch_bounds__((p2_threads<R, LOG2L, STRIDED>())) void k_fft_p2(
     if (o >= fp.outer || ic >= fp.inner) continue;
     cplx<R> v = buf[((fp.out_off + i) & (L - 1)) * SW + w];
     if (dcmode == 2) v = cscale(v, (R)(linefac[w] * dc[n0 + n1 + i]));
-    out[((size_t)o * fp.nout + i) * fp.inner + ic] = v;
+    out[((size_t)o * fp.nout + i) * fp.inner + ic] = cplx<Ro>{(Ro)v.re, (Ro)v.im};
   }
 }
 
-template <class Ri, class R, int LOG2L, bool STRIDED>
+template <class Ri, class Ro, int LOG2L, bool STRIDED>
 hipError_t fft_p2s(const Plan &p, const FftPass &fp, const void *in, void *out, int tw_index, int dcmode) {
-  constexpr int W = p2_lines<R, LOG2L, STRIDED>();
+  constexpr int W = p2_lines<double, LOG2L, STRIDED>();
   constexpr int SW = p2_stride<W, STRIDED>();
-  constexpr int NT = p2_threads<R, LOG2L, STRIDED>();
+  constexpr int NT = p2_threads<double, LOG2L, STRIDED>();
   const int groups = STRIDED ? fp.outer * ((fp.inner + W - 1) / W) : (fp.outer + W - 1) / W;
-  const size_t lds = ((size_t)(1 << LOG2L) * SW + (1 << LOG2L)) * sizeof(cplx<R>);
-  k_fft_p2<Ri, R, LOG2L, STRIDED><<<groups, NT, lds, p.stream>>>(
-      (const cplx<Ri> *)in, (cplx<R> *)out, fp, (const cplx<double> *)p.twiddle + p.tw_off[tw_index],
+  const size_t lds = ((size_t)(1 << LOG2L) * SW + (1 << LOG2L)) * sizeof(cplx<double>);
+  k_fft_p2<Ri, Ro, LOG2L, STRIDED><<<groups, NT, lds, p.stream>>>(
+      (const cplx<Ri> *)in, (cplx<Ro> *)out, fp, (const cplx<double> *)p.twiddle + p.tw_off[tw_index],
       (const double *)p.deconv, dcmode, p.n[0], p.n[1]);
   return hipGetLastError();
 }
 
-template <class Ri, class R, int LOG2L>
+template <class Ri, class Ro, int LOG2L>
 hipError_t fft_p2(const Plan &p, const FftPass &fp, const void *in, void *out, int tw_index, int dcmode) {
-  if (fp.inner > 1) return fft_p2s<Ri, R, LOG2L, true>(p, fp, in, out, tw_index, dcmode);
-  return fft_p2s<Ri, R, LOG2L, false>(p, fp, in, out, tw_index, dcmode);
+  if (fp.inner > 1) return fft_p2s<Ri, Ro, LOG2L, true>(p, fp, in, out, tw_index, dcmode);
+  return fft_p2s<Ri, Ro, LOG2L, false>(p, fp, in, out, tw_index, dcmode);
 }
 
-template <class Ri, class R>
+template <class Ri, class Ro>
 hipError_t fft_pow2(const Plan &p, const FftPass &fp, const void *in, void *out, int tw_index, int dcmode,
                     bool *done) {
   *done = true;
   switch (fp.L) {
-    case 8: return fft_p2<Ri, R, 3>(p, fp, in, out, tw_index, dcmode);
-    case 16: return fft_p2<Ri, R, 4>(p, fp, in, out, tw_index, dcmode);
-    case 32: return fft_p2<Ri, R, 5>(p, fp, in, out, tw_index, dcmode);
-    case 64: return fft_p2<Ri, R, 6>(p, fp, in, out, tw_index, dcmode);
-    case 128: return fft_p2<Ri, R, 7>(p, fp, in, out, tw_index, dcmode);
-    case 256: return fft_p2<Ri, R, 8>(p, fp, in, out, tw_index, dcmode);
-    case 512: return fft_p2<Ri, R, 9>(p, fp, in, out, tw_index, dcmode);
-    case 1024: return fft_p2<Ri, R, 10>(p, fp, in, out, tw_index, dcmode);
-    case 2048: return fft_p2<Ri, R, 11>(p, fp, in, out, tw_index, dcmode);
+    case 8: return fft_p2<Ri, Ro, 3>(p, fp, in, out, tw_index, dcmode);
+    case 16: return fft_p2<Ri, Ro, 4>(p, fp, in, out, tw_index, dcmode);
+    case 32: return fft_p2<Ri, Ro, 5>(p, fp, in, out, tw_index, dcmode);
+    case 64: return fft_p2<Ri, Ro, 6>(p, fp, in, out, tw_index, dcmode);
+    case 128: return fft_p2<Ri, Ro, 7>(p, fp, in, out, tw_index, dcmode);
+    case 256: return fft_p2<Ri, Ro, 8>(p, fp, in, out, tw_index, dcmode);
+    case 512: return fft_p2<Ri, Ro, 9>(p, fp, in, out, tw_index, dcmode);
+    case 1024: return fft_p2<Ri, Ro, 10>(p, fp, in, out, tw_index, dcmode);
+    case 2048: return fft_p2<Ri, Ro, 11>(p, fp, in, out, tw_index, dcmode);
     default: *done = false; return hipSuccess;
   }
 }
 
 }  // namespace
 
-template <class Ri, class R>
+template <class Ri, class Ro>
 hipError_t fft_typed(const Plan &p, const FftPass &fp, const void *in, void *out, int tw_index, int dcmode) {
   bool done = false;
-  const hipError_t e = fft_pow2<Ri, R>(p, fp, in, out, tw_index, dcmode, &done);
+  const hipError_t e = fft_pow2<Ri, Ro>(p, fp, in, out, tw_index, dcmode, &done);
   if (done) return e;
   const int groups = fp.inner > 1 ? fp.outer * ((fp.inner + fp.W - 1) / fp.W) : (fp.outer + fp.W - 1) / fp.W;
-  const size_t lds = (2 * (size_t)fp.L * fp.W + fp.L) * sizeof(cplx<R>);
-  k_fft<Ri, R><<<groups, 256, lds, p.stream>>>((const cplx<Ri> *)in, (cplx<R> *)out, fp,
-                                               (const cplx<double> *)p.twiddle + p.tw_off[tw_index],
-                                               (const double *)p.deconv, dcmode, p.n[0], p.n[1]);
+  const size_t lds = (2 * (size_t)fp.L * fp.W + fp.L) * sizeof(cplx<double>);
+  k_fft<Ri, Ro><<<groups, 256, lds, p.stream>>>((const cplx<Ri> *)in, (cplx<Ro> *)out, fp,
+                                                (const cplx<double> *)p.twiddle + p.tw_off[tw_index],
+                                                (const double *)p.deconv, dcmode, p.n[0], p.n[1]);
   return hipGetLastError();
 }
 
+// in_f64 / out_f64: element types read and written; the transform runs in FP64.
 hipError_t launch_fft_pass(const Plan &p, const FftPass &fp, const void *in, void *out, int tw_index, int dcmode,
                            int in_f64, int out_f64) {
   if (in_f64 && out_f64) return fft_typed<double, double>(p, fp, in, out, tw_index, dcmode);

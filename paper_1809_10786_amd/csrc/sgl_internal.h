@@ -136,7 +136,7 @@ hipError_t launch_point_radius(const Plan &p, const void *xyz, double *partial, 
 hipError_t launch_point_prep(Plan &p, const void *xyz, uint32_t *keys, int32_t *idx, void *unsorted);
 hipError_t launch_point_sort(Plan &p, uint32_t *keys, int32_t *idx, void *unsorted);
 hipError_t launch_conv_radial(const Plan &p, const void *fhat);
-hipError_t launch_conv_polar(const Plan &p, void *eta);
+hipError_t launch_conv_polar(const Plan &p, void *eta, int eta_f64);
 hipError_t launch_conv_polar_adj(const Plan &p, const void *eta, int eta_f64);
 hipError_t launch_conv_radial_adj(const Plan &p, void *fhat);
 // One FFT pass; in_f64/out_f64 select double or float elements (float input

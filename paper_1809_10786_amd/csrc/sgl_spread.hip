@@ -226,7 +226,8 @@ __global__ __launch_bounds__(GatherShape<Q2>::threads) void k_gather_mfma(const 
   for (int w = 0; w < NW; ++w) bmx = fmaxf(bmx, red[w]);
   int ex = 0;
   if (bmx > 0.0f) frexpf(bmx, &ex);     // bmx = m 2^ex, m in [0.5, 1)
-  const float sc = ldexpf(1.0f, 14 - ex);  // scaled maximum in [2^13, 2^14)
+  // scaled maximum in [2^13, 2^14) (the FP32 range caps the scale for denormal boxes)
+  const float sc = ldexpf(1.0f, min(14 - ex, 126));
   // 3. FP16 hi/lo planes
 #pragma unroll
   for (int u = 0; u < Sh::KB; ++u) {
@@ -703,7 +704,7 @@ constexpr int kSpreadThreads = 256;  // 4 waves
 constexpr int kSB = 128;             // points staged at once
 constexpr int kTS = kSB + 4;         // floats per weight-table row (conflict-free b128 reads)
 constexpr int kBS = kSB + 8;         // halves per B-plane column (conflict-free b128 reads)
-constexpr int kNoExp = -100;         // running exponent before the first nonzero sample
+constexpr int kNoExp = -200;         // running exponent before the first nonzero sample
 
 
 // FP16 hi + lo parts of eight FP32 values (hi rounded to nearest, lo = the
@@ -828,7 +829,7 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_mfma(const cplx<float
               }
         }
         E = eb;
-        sc = ldexpf(1.0f, 14 - E);
+        sc = ldexpf(1.0f, min(14 - E, 126));
       }
     }
     // 2. B planes: work item -> column c = i2, points 8 pg .. 8 pg + 7
@@ -899,8 +900,9 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_mfma(const cplx<float
     }
     __syncthreads();  // the batch's tables are consumed
   }
-  // D[4h + j][pl] of every row block to the chunk's box in the staging area
-  const float inv = 1.0f / (4096.0f * sc);
+  // D[4h + j][pl] of every row block to the chunk's box in the staging area;
+  // 1 / (2^12 sc) applied as two normal powers of two
+  const float inv = 1.0f / sc;
   cplx<float> *out = staging + (size_t)blockIdx.x * nrow * X;
 #pragma unroll
   for (int r = 0; r < RBW; ++r) {
@@ -913,7 +915,9 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_mfma(const cplx<float
 #pragma unroll
           for (int n = 0; n < 2; ++n) {
             const int col = 16 * n + pl;
-            if (col < X) out[row * X + col] = cplx<float>{acc[r][n][0][j] * inv, acc[r][n][1][j] * inv};
+            if (col < X)
+              out[row * X + col] = cplx<float>{acc[r][n][0][j] * (1.0f / 4096.0f) * inv,
+                                               acc[r][n][1][j] * (1.0f / 4096.0f) * inv};
           }
         }
       }

@@ -80,6 +80,19 @@ def test_plan_rejects_bad_arguments(B, sigma, q, prec, flags, M):
     assert h.value is None
 
 
+@pytest.mark.parametrize("B", [7, 13, 11])
+def test_plan_rejects_fft_lengths_with_large_prime_factors(B):
+    """The FFT handles lengths 2^a 3^b 5^c; sigma * 2B with another prime
+    factor is refused on the host, before any device call."""
+    sgl = _lib()
+    L = sgl.lib()
+    prm = sgl.SglParams(B, 2, 3, 0.0, 0, 0)
+    h = ctypes.c_void_p(123)
+    st = L.sgl_plan(ctypes.byref(h), ctypes.byref(prm), 10, ctypes.c_void_p(0x1000), None)
+    assert st == sgl.SGL_E_UNSUPPORTED
+    assert h.value is None
+
+
 def test_null_arguments():
     sgl = _lib()
     L = sgl.lib()

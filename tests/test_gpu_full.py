@@ -1,0 +1,146 @@
+"""GPU parity at the full workload sizes and on the FP32 matrix-core path.
+
+* the throughput workload (B=64, M=4e6, FP32 and FP64) in the launch
+  configuration the benchmark times, the B=32, M=1e6 mixed point set and the
+  B=48, M=2e6 anisotropic mixture: forward outputs at sampled points against
+  the direct sum (Def. 1.3), the adjoint on samples supported on a subset of
+  the points against the direct adjoint, and the adjoint identity
+  <Lambda fhat, y> = <fhat, Lambda^H y> with every point;
+* the FP32 NFFT stage (matrix-core gather and spread, tiles of 8^3 cells)
+  against the FP64 stepwise Gaussian NFFT: several tiles with ragged point
+  counts, one tile holding more than one chunk of points, all-zero input and
+  inputs scaled by 2^+-80.
+Tolerances: FP32 1e-5 relative (l2 and max), FP64 at q=6 2e-6 (the Gaussian
+window's truncation error, Theorem 2.7), identity 2e-6 (FP32) / 1e-12 (FP64)
+relative to |y| |Lambda fhat|.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import stepwise as sw
+from tests import workloads as wl
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def relinf(a, b):
+    return float(np.abs(np.asarray(a) - np.asarray(b)).max() / np.abs(np.asarray(b)).max())
+
+
+def dev(x, dtype):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(device="cuda", dtype=dtype)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy().astype(np.complex128)
+
+
+def as_used(x, prec):
+    """Inputs exactly as the library sees them."""
+    if prec == "f64":
+        return x
+    if np.iscomplexobj(x):
+        return x.astype(np.complex64).astype(np.complex128)
+    return x.astype(np.float32).astype(np.float64)
+
+
+def check_workload(name, prec, seed, nsample, tol, idtol):
+    import paper_1809_10786_amd as sgl
+
+    w, pts, fh, y = wl.workload(name, seed=seed)
+    B = w["B"]
+    say(f"full {name} {prec} B={B} M={len(pts)} q={w['q']}")
+    rdt, cdt = (torch.float64, torch.complex128) if prec == "f64" else (torch.float32, torch.complex64)
+    p = sgl.Plan(dev(pts, rdt), B, sigma=w["sigma"], q=w["q"], precision=prec)
+    if prec == "f32":
+        assert p.info()["gather_mode"] == 2  # the matrix-core gather and spread
+    pu, fhu = as_used(pts, prec), as_used(fh, prec)
+    f = host(p.forward(dev(fh, cdt)))
+    idx = np.sort(np.random.default_rng(seed + 7).choice(len(pts), nsample, replace=False))
+    f0 = oracle.direct_forward(B, pu[idx], fhu)
+    say(f"  forward rel l2 {rel(f[idx], f0):.3g} max {relinf(f[idx], f0):.3g}")
+    assert rel(f[idx], f0) < tol and relinf(f[idx], f0) < tol
+    ys = np.zeros(len(pts), dtype=np.complex128)
+    ys[idx] = y[idx]
+    g = host(p.adjoint(dev(ys, cdt)))
+    g0 = oracle.direct_adjoint(B, pu[idx], as_used(ys, prec)[idx])
+    say(f"  adjoint rel l2 {rel(g, g0):.3g} max {relinf(g, g0):.3g}")
+    assert rel(g, g0) < tol and relinf(g, g0) < tol
+    # adjoint identity with every point
+    g = host(p.adjoint(dev(y, cdt)))
+    yu = as_used(y, prec)
+    lhs, rhs = np.vdot(yu, f), np.vdot(g, fhu)
+    say(f"  identity {abs(lhs - rhs) / (np.linalg.norm(yu) * np.linalg.norm(f)):.3g}")
+    assert abs(lhs - rhs) < idtol * np.linalg.norm(yu) * np.linalg.norm(f)
+    p.close()
+
+
+def test_b64_m4e6_f32_launch_configuration():
+    check_workload("b64_m4e6_f32", "f32", 11, 400, 1e-5, 2e-6)
+
+
+def test_b64_m4e6_f64():
+    check_workload("b64_m4e6_f64", "f64", 12, 400, 2e-6, 1e-12)
+
+
+@pytest.mark.parametrize("prec,tol,idtol", [("f32", 1e-5, 2e-6), ("f64", 2e-6, 1e-12)])
+def test_b32_m1e6_mixed(prec, tol, idtol):
+    check_workload("b32_m1e6_" + prec, prec, 13, 1500, tol, idtol)
+
+
+def test_b48_m2e6_anisotropic_mixture_f32():
+    check_workload("b48_m2e6_f32", "f32", 14, 800, 1e-5, 2e-6)
+
+
+# ------------------------------------------------------------ FP32 NFFT stage
+
+
+def stage_points(seed):
+    """2000 Gaussian points plus 2600 points packed into one tile (more than
+    two chunks of 1024), at rho = 1.1 max r."""
+    rng = np.random.default_rng(seed)
+    a = wl.gaussian_points(2000, seed)
+    c = np.array([0.35, -0.2, 0.5]) + 1e-3 * rng.standard_normal((2600, 3))
+    return np.concatenate([a, c], axis=0)
+
+
+@pytest.mark.parametrize("B", [8, 12])
+def test_fp32_nfft_stage_matrix_cores(B):
+    import paper_1809_10786_amd as sgl
+
+    q = 6
+    pts = stage_points(50 + B)
+    rho = 1.1 * np.linalg.norm(pts, axis=1).max()
+    say(f"fp32 nfft stage B={B} M={len(pts)}")
+    p = sgl.Plan(dev(pts, torch.float32), B, q=q, rho=rho, precision="f32")
+    info = p.info()
+    assert info["gather_mode"] == 2 and (info["L0"], info["L1"], info["L2"]) == (8, 8, 8)
+    t = sw.x_tilde(as_used(pts, "f32"), p.rho)
+    rng = np.random.default_rng(60 + B)
+    eta = as_used(rng.standard_normal(p.eta_shape) + 1j * rng.standard_normal(p.eta_shape), "f32")
+    y = as_used(wl.samples(len(pts), 70 + B), "f32")
+    f0 = sw.nfft(eta, t, 2, q)
+    e0 = sw.nfft_adjoint(y, t, p.eta_shape, 2, q).reshape(-1)
+    for scale in (1.0, 2.0 ** 80, 2.0 ** -80):
+        f = host(p.nfft_forward(dev(eta * scale, torch.complex64))) / scale
+        e = host(p.nfft_adjoint(dev(y * scale, torch.complex64))).reshape(-1) / scale
+        say(f"  scale {scale:.3g}: forward {rel(f, f0):.3g} / {relinf(f, f0):.3g}, "
+            f"adjoint {rel(e, e0):.3g} / {relinf(e, e0):.3g}")
+        assert rel(f, f0) < 1e-5 and relinf(f, f0) < 1e-5
+        assert rel(e, e0) < 1e-5 and relinf(e, e0) < 1e-5
+    z = host(p.nfft_forward(torch.zeros(p.eta_shape, dtype=torch.complex64, device="cuda")))
+    assert not np.any(z)
+    z = host(p.nfft_adjoint(torch.zeros(len(pts), dtype=torch.complex64, device="cuda")))
+    assert not np.any(z)
+    p.close()

@@ -56,6 +56,27 @@ def mixed_points(M, seed, frac_ball=0.1, radius=4.0):
     return np.concatenate([g, b], axis=0)
 
 
+def mixture_points(M, seed, k=3, diag_lo=0.3, diag_hi=2.0):
+    """Anisotropic Gaussian mixture: k components with equal weights, means
+    iid U[-1, 1]^3 and diagonal covariances with entries iid U[diag_lo, diag_hi]."""
+    rng = np.random.default_rng(seed)
+    means = rng.uniform(-1.0, 1.0, (k, 3))
+    cov = rng.uniform(diag_lo, diag_hi, (k, 3))
+    comp = rng.integers(0, k, M)
+    return means[comp] + rng.standard_normal((M, 3)) * np.sqrt(cov[comp])
+
+
+def clustered_points(M, seed, k=8):
+    """Gaussian mixture of k isotropic clusters, weights ~ Dirichlet(1), means
+    iid N(0, I/2), cluster variances iid U[0.02, 0.2]."""
+    rng = np.random.default_rng(seed)
+    w = rng.dirichlet(np.ones(k))
+    means = rng.standard_normal((k, 3)) * np.sqrt(0.5)
+    var = rng.uniform(0.02, 0.2, k)
+    comp = rng.choice(k, M, p=w)
+    return means[comp] + rng.standard_normal((M, 3)) * np.sqrt(var[comp])[:, None]
+
+
 def samples(M, seed):
     """Adjoint input y: iid complex N(0, 1)."""
     rng = np.random.default_rng(seed)
@@ -72,6 +93,8 @@ WORKLOADS = {
     # Throughput workload: B=64, M=4e6 Gaussian points, n^-1.5, FP32, q=6.
     "b64_m4e6_f32": dict(B=64, M=4_000_000, points="gaussian", decay=1.5, sigma=2, q=6, prec="f32"),
     "b64_m4e6_f64": dict(B=64, M=4_000_000, points="gaussian", decay=1.5, sigma=2, q=6, prec="f64"),
+    # B=48, M=2e6 FP32 points from a 3-component anisotropic Gaussian mixture, n^-1.5, q=6.
+    "b48_m2e6_f32": dict(B=48, M=2_000_000, points="aniso3", decay=1.5, sigma=2, q=6, prec="f32"),
 }
 
 
@@ -80,6 +103,10 @@ def make_points(kind, M, seed):
         return gaussian_points(M, seed)
     if kind == "mixed":
         return mixed_points(M, seed)
+    if kind == "aniso3":
+        return mixture_points(M, seed)
+    if kind == "clustered8":
+        return clustered_points(M, seed)
     if kind.startswith("ball"):
         return ball_points(M, float(kind[4:]), seed)
     raise ValueError(kind)
