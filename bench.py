@@ -147,7 +147,11 @@ def summarize_profiles(kt_dir, fetch_dir, write_dir, out_md, command):
     import glob
 
     def one(pattern):
-        return glob.glob(os.path.join(pattern))[0]
+        d, name = os.path.split(pattern)
+        hits = sorted(glob.glob(os.path.join(d, "**", name), recursive=True))
+        if not hits:
+            raise FileNotFoundError(pattern)
+        return hits[0]
 
     stats = list(csv.DictReader(open(one(os.path.join(kt_dir, "*_kernel_stats.csv")))))
     counters = {}
