@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="b64_m4e6_f32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--conv-split16", action="store_true",
+                    help="conversion products on the FP16 matrix cores with hi/lo split operands")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--check-points", type=int, default=2000)
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -235,7 +237,7 @@ def main():
     dy = torch.from_numpy(y).to("cuda", cdt)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    plan = sgl.Plan(dpts, B, sigma=w["sigma"], q=q, precision=prec)
+    plan = sgl.Plan(dpts, B, sigma=w["sigma"], q=q, precision=prec, conv_split16=a.conv_split16)
     torch.cuda.synchronize()
     plan_ms = (time.perf_counter() - t0) * 1e3
     info = plan.info()
@@ -330,7 +332,8 @@ def main():
         "dtype": prec,
         "data": "synthetic",
         "config": {"workload": a.workload, "B": B, "M": M, "sigma": w["sigma"], "q": q,
-                   "points": w["points"], "coeff_decay": w["decay"], "rho": plan.rho},
+                   "points": w["points"], "coeff_decay": w["decay"], "rho": plan.rho,
+                   "conversion": "fp16-split-mfma" if a.conv_split16 else "fp64"},
         "roofline": roof,
         "hbm_frac_step": hbm_frac_step,
         "cpu_baseline": cpu,

@@ -56,6 +56,13 @@ typedef enum { SGL_F64 = 0, SGL_F32 = 1 } sgl_precision;
  * to separate the NFFT error from the rest, Section 8, fourth test).  O(B^3)
  * work per point: for testing only. */
 #define SGL_FLAG_EXACT_NDFT (1u << 0)
+/* Conversion products (Thm. 6.2, Cor. 6.3) on the FP16 matrix cores with hi/lo
+ * split operands and FP32 accumulation (tables built in long double and split
+ * at plan time, per row; data split per column).  Keeps about 22 bits of every
+ * product; the conversion sums cancel strongly when the radial functions grow
+ * towards rho, so results are less accurate than the default FP64 products
+ * (errors per workload are stated with the design notes). */
+#define SGL_FLAG_CONV_SPLIT16 (1u << 1)
 
 typedef struct {
   int32_t B;          /* bandwidth, 2 <= B <= 256 (Section 6 assumes B >= 2)              */

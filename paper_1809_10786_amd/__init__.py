@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(HERE, "libsgl.so")
 SGL_OK, SGL_E_INVAL, SGL_E_RANGE, SGL_E_NOMEM, SGL_E_DEVICE, SGL_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 SGL_F64, SGL_F32 = 0, 1
 SGL_FLAG_EXACT_NDFT = 1
+SGL_FLAG_CONV_SPLIT16 = 2
 
 # Every symbol include/sgl.h declares.
 SYMBOLS = (
@@ -101,9 +102,11 @@ class Plan:
     points    : torch tensor (M, 3), float64 for precision "f64", float32 for "f32", on the GPU
     B         : bandwidth; sigma, q: NFFT oversampling and cutoff; rho <= 0 picks max |x_i|
     exact_ndft: evaluate the trigonometric polynomial exactly (test mode)
+    conv_split16: conversion products on the FP16 matrix cores with hi/lo split operands
     """
 
-    def __init__(self, points, B, sigma=2, q=6, rho=0.0, precision="f64", exact_ndft=False, stream=None):
+    def __init__(self, points, B, sigma=2, q=6, rho=0.0, precision="f64", exact_ndft=False, conv_split16=False,
+                 stream=None):
         import torch
 
         self._torch = torch
@@ -119,7 +122,7 @@ class Plan:
         self.device = points.device
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         prm = SglParams(self.B, int(sigma), int(q), float(rho), SGL_F64 if precision == "f64" else SGL_F32,
-                        SGL_FLAG_EXACT_NDFT if exact_ndft else 0)
+                        (SGL_FLAG_EXACT_NDFT if exact_ndft else 0) | (SGL_FLAG_CONV_SPLIT16 if conv_split16 else 0))
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             st = lib().sgl_plan(ctypes.byref(h), ctypes.byref(prm), self.M, ctypes.c_void_p(points.data_ptr()),

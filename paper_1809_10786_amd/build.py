@@ -27,7 +27,8 @@ FLAGS = [
     "-I" + CSRC,
 ]
 
-SOURCES = ["sgl_api.cpp", "sgl_tables.cpp", "sgl_points.hip", "sgl_conv.hip", "sgl_fft.hip", "sgl_spread.hip"]
+SOURCES = ["sgl_api.cpp", "sgl_tables.cpp", "sgl_points.hip", "sgl_conv.hip", "sgl_conv_products.hip", "sgl_fft.hip",
+           "sgl_spread.hip"]
 
 
 def _compile(src, verbose):

@@ -64,6 +64,7 @@ void free_plan(Plan &p) {
                   p.zeta, p.eta, p.bufX, p.bufY, p.ptsxyz, p.tile_chunk, p.staging};
   for (void *b : bufs)
     if (b) hipFree(b);
+  free_conv_tables(p);
 }
 
 template <class T>
@@ -201,6 +202,10 @@ sgl_status build_tables(Plan &p) {
   build_deconv(p, dc);
   SGL_TRY(upload_real<double>(p, &p.krad, kr));
   SGL_TRY(upload_real<double>(p, &p.kpol, kp));
+  {
+    const sgl_status st = build_conv_tables(p, kr, kp);
+    if (st != SGL_OK) return st;
+  }
   SGL_TRY(upload_real<double>(p, &p.deconv, dc));
   SGL_TRY(upload_twiddles(p));
   return SGL_OK;
@@ -328,15 +333,20 @@ struct Stage {
   } while (0)
 
 // eta_f64: element type of the eta output (the products themselves run in FP64).
+// The four products run as batched matrix-core tiles (FP64, or FP16 hi/lo
+// with SGL_FLAG_CONV_SPLIT16); unfold and fold map the compact zeta to and
+// from eta.
 sgl_status conv_fwd(Plan &p, const void *fhat, void *eta, int eta_f64) {
-  SGL_STAGE(SGL_STAGE_CONV_RADIAL, launch_conv_radial(p, fhat));
-  SGL_STAGE(SGL_STAGE_CONV_POLAR, launch_conv_polar(p, eta, eta_f64));
+  SGL_STAGE(SGL_STAGE_CONV_RADIAL, launch_conv_product(p, 0, fhat, p.beta));
+  SGL_STAGE(SGL_STAGE_CONV_POLAR, launch_conv_product(p, 1, p.beta, p.zeta));
+  SGL_STAGE(SGL_STAGE_CONV_POLAR, launch_conv_unfold(p, eta, eta_f64));
   return SGL_OK;
 }
 
 sgl_status conv_adj(Plan &p, const void *eta, int eta_f64, void *fhat) {
-  SGL_STAGE(SGL_STAGE_CONV_POLAR_ADJ, launch_conv_polar_adj(p, eta, eta_f64));
-  SGL_STAGE(SGL_STAGE_CONV_RADIAL_ADJ, launch_conv_radial_adj(p, fhat));
+  SGL_STAGE(SGL_STAGE_CONV_POLAR_ADJ, launch_conv_fold_eta(p, eta, eta_f64));
+  SGL_STAGE(SGL_STAGE_CONV_POLAR_ADJ, launch_conv_product(p, 2, p.zeta, p.beta));
+  SGL_STAGE(SGL_STAGE_CONV_RADIAL_ADJ, launch_conv_product(p, 3, p.beta, fhat));
   return SGL_OK;
 }
 
@@ -419,7 +429,7 @@ sgl_status sgl_plan(sgl_plan_t *out, const sgl_params *prm, int64_t M, const voi
   if (prm->sigma < 2 || prm->sigma > 4) return SGL_E_INVAL;
   if (prm->q < 1 || prm->q > 16 || 2 * prm->q > prm->sigma * 2 * prm->B) return SGL_E_INVAL;
   if (prm->precision != SGL_F64 && prm->precision != SGL_F32) return SGL_E_INVAL;
-  if (prm->flags & ~(uint32_t)SGL_FLAG_EXACT_NDFT) return SGL_E_INVAL;
+  if (prm->flags & ~(uint32_t)(SGL_FLAG_EXACT_NDFT | SGL_FLAG_CONV_SPLIT16)) return SGL_E_INVAL;
   if (!std::isfinite(prm->rho)) return SGL_E_INVAL;
   if (M < 1 || M > 0x7fffffffLL) return SGL_E_INVAL;
   sgl_plan_s *h = new (std::nothrow) sgl_plan_s;

@@ -83,6 +83,18 @@ struct Profiler {
 };
 
 // The plan (opaque to callers).
+// Table operand and tile list of one conversion product (sgl_conv_products.hip).
+struct ConvGroup {
+  int32_t Mpad, Kpad;  // padded rows (16) and columns (32) of the table operand
+  int64_t plane_off;   // first half of the hi plane; the lo plane follows (Mpad * Kpad halves)
+  int32_t rexp_off;    // first row exponent
+  int32_t pad_;
+};
+struct ConvTab {
+  void *groups = nullptr, *planes = nullptr, *rexp = nullptr, *tiles = nullptr;
+  int ntiles = 0;
+};
+
 struct Plan {
   // parameters
   int B = 0, sigma = 2, q = 6, prec = SGL_F64;
@@ -116,6 +128,7 @@ struct Plan {
   void *staging = nullptr;        // nchunks window boxes (tiled scatter)
   int F[3] = {8, 8, 8};           // fold block edges (stored cells)
   void *krad = nullptr, *kpol = nullptr;  // conversion matrices (always FP64)
+  ConvTab conv[4];                       // conversion products: FP64 or FP16 hi/lo table operands
   void *deconv = nullptr;                 // n0 + n1 + n2 reals
   void *twiddle = nullptr;                // per dimension: N_j complex double
   int64_t tw_off[3] = {0, 0, 0};
@@ -135,10 +148,11 @@ struct Plan {
 hipError_t launch_point_radius(const Plan &p, const void *xyz, double *partial, int nblocks);
 hipError_t launch_point_prep(Plan &p, const void *xyz, uint32_t *keys, int32_t *idx, void *unsorted);
 hipError_t launch_point_sort(Plan &p, uint32_t *keys, int32_t *idx, void *unsorted);
-hipError_t launch_conv_radial(const Plan &p, const void *fhat);
-hipError_t launch_conv_polar(const Plan &p, void *eta, int eta_f64);
-hipError_t launch_conv_polar_adj(const Plan &p, const void *eta, int eta_f64);
-hipError_t launch_conv_radial_adj(const Plan &p, void *fhat);
+hipError_t launch_conv_product(const Plan &p, int mode, const void *in, void *out);
+hipError_t launch_conv_unfold(const Plan &p, void *eta, int eta_f64);
+hipError_t launch_conv_fold_eta(const Plan &p, const void *eta, int eta_f64);
+sgl_status build_conv_tables(Plan &p, const std::vector<long double> &kr, const std::vector<long double> &kp);
+void free_conv_tables(Plan &p);
 // One FFT pass; in_f64/out_f64 select double or float elements (float input
 // with double output widens; the transform runs in the output precision).
 hipError_t launch_fft_pass(const Plan &p, const FftPass &fp, const void *in, void *out, int tw_index, int dcmode,
