@@ -128,6 +128,23 @@ sgl_status sgl_nfft_forward(sgl_plan_t plan, const void *eta_dev, void *f_dev);
 /* Stage: adjoint of sgl_nfft_forward: f (M complex) -> eta (reduced grid). */
 sgl_status sgl_nfft_adjoint(sgl_plan_t plan, const void *f_dev, void *eta_dev);
 
+/* Gradient with respect to the point positions (rho held fixed) of a real
+ * loss L(f), f = Lambda fhat (Def. 1.3), given g = dL/d conj(f):
+ *   grad[3i + c] = Re(conj(g_i) d f_i / d x_ic),
+ * the conjugate-Wirtinger convention (the gradient with respect to fhat is
+ * sgl_adjoint(g)).  f_i is the NFFT approximation of Section 2, so the window
+ * derivative d/du exp(-(u - l)^2 / (2 lambda)) = -((u - l) / lambda) exp(...)
+ * replaces the window, chained through x -> (r, theta, phi) -> x~ (eq. x_tilde)
+ * -> u = N x~ / (2 pi).  fhat_dev: Nc complex; points_dev: the M x 3 points the
+ * plan was made with (caller order, plan precision); g_dev: M complex; grad_dev:
+ * M x 3 reals (plan precision), caller order.  Points on the z axis, at the
+ * origin or with r >= rho get NaN (the angles are not differentiable there;
+ * make the plan with rho slightly above max |x| to differentiate the outermost
+ * point).  SGL_E_UNSUPPORTED with SGL_FLAG_EXACT_NDFT; SGL_E_INVAL for null or
+ * overlapping grad_dev.  Enqueued on the plan's stream. */
+sgl_status sgl_grad_points(sgl_plan_t plan, const void *fhat_dev, const void *points_dev, const void *g_dev,
+                           void *grad_dev);
+
 /* The rho the plan uses (host pointer out). */
 sgl_status sgl_plan_rho(sgl_plan_t plan, double *rho);
 

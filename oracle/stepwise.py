@@ -104,6 +104,43 @@ def sgl_basis(B, points):
     return out
 
 
+def sgl_basis_grad(B, points):
+    """d H_nlm(x) / d x_c for c = 0, 1, 2: array (3, M, Nc).
+
+    Chain rule through (r, theta, phi): the radial factor N_nl L_k^(a)(r^2) r^l
+    (k = n-l-1, a = l+1/2) differentiates with d/dt L_k^(a)(t) = -L_{k-1}^(a+1)(t);
+    the angular factor Y_lm with scipy's derivatives in theta and phi.
+    Undefined on the z axis and at the origin, where phi or theta is.
+    """
+    p = np.asarray(points, dtype=np.float64)
+    x, y, z = p[:, 0], p[:, 1], p[:, 2]
+    r, th, ph = spherical(p)
+    rxy = np.hypot(x, y)
+    dr = np.stack([x / r, y / r, z / r])
+    dth = np.stack([x * z / (r * r * rxy), y * z / (r * r * rxy), -rxy / (r * r)])
+    dph = np.stack([-y / (rxy * rxy), x / (rxy * rxy), np.zeros_like(x)])
+    ns, ls, ms = coeff_table(B)
+    out = np.empty((3, len(r), len(ns)), dtype=np.complex128)
+    for mu, (n, l, m) in enumerate(zip(ns, ls, ms)):
+        k, a = n - l - 1, l + 0.5
+        t = r * r
+        L = sp.eval_genlaguerre(k, a, t)
+        dL = -sp.eval_genlaguerre(k - 1, a + 1, t) if k >= 1 else np.zeros_like(t)
+        c = N_nl(n, l)
+        R = c * L * r ** l
+        dR = c * (2 * r * dL * r ** l + (l * L * r ** (l - 1) if l > 0 else 0.0))
+        Y, dY = sp.sph_harm_y(l, m, th, ph, diff_n=1)  # dY: (M, 2) = d/dtheta, d/dphi
+        dYth, dYph = dY[..., 0], dY[..., 1]
+        out[:, :, mu] = dR * Y * dr + R * dYth * dth + R * dYph * dph
+    return out
+
+
+def forward_grad(B, points, fhat):
+    """d f(x_i) / d x_ic of f = Lambda fhat (Def. 1.3), shape (M, 3), complex."""
+    G = sgl_basis_grad(B, points)
+    return np.einsum("cmn,n->mc", G, np.asarray(fhat, dtype=np.complex128))
+
+
 # ----------------------------------------------------------------------------
 # DCT (Def. 3.1)
 # ----------------------------------------------------------------------------

@@ -6,6 +6,7 @@ HIP kernels.  PyTorch provides device memory and the current stream.  There
 is no fallback -- if the library is missing, importing the binding raises.
 """
 import ctypes
+import functools
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -21,7 +22,7 @@ SYMBOLS = (
     "sgl_num_coeffs", "sgl_coeff_index", "sgl_eta_dims", "sgl_plan", "sgl_forward", "sgl_adjoint",
     "sgl_conv_forward", "sgl_conv_adjoint", "sgl_nfft_forward", "sgl_nfft_adjoint", "sgl_plan_rho",
     "sgl_plan_info", "sgl_plan_profile", "sgl_plan_stage_times", "sgl_destroy", "sgl_status_string",
-    "sgl_last_error",
+    "sgl_last_error", "sgl_grad_points",
 )
 
 STAGES = ("conv_radial", "conv_polar", "fft_A", "fft_B", "fft_C", "gather", "scatter", "fft_Ch", "fft_Bh",
@@ -69,6 +70,7 @@ def lib():
         L.sgl_destroy.argtypes, L.sgl_destroy.restype = [vp], ctypes.c_int
         L.sgl_status_string.argtypes, L.sgl_status_string.restype = [ctypes.c_int], ctypes.c_char_p
         L.sgl_last_error.argtypes, L.sgl_last_error.restype = [], ctypes.c_char_p
+        L.sgl_grad_points.argtypes, L.sgl_grad_points.restype = [vp, vp, vp, vp, vp], ctypes.c_int
         _lib = L
     return _lib
 
@@ -217,6 +219,24 @@ class Plan:
         self._call("sgl_nfft_adjoint", x, y)
         return y.view(self.eta_shape)
 
+    def grad_points(self, fhat, points, g, out=None):
+        """Re(conj(g_i) d f_i / d x_i), (M, 3): the gradient with respect to the
+        point positions (rho fixed) of a real loss with dL/d conj(f) = g; points
+        are the tensor the plan was made with."""
+        x = self._in(fhat, self.nc, "fhat")
+        gg = self._in(g, self.M, "g")
+        if not points.is_cuda or points.dtype != self.real_dtype or points.shape != (self.M, 3):
+            raise ValueError(f"points must be the plan's CUDA tensor (M, 3) of {self.real_dtype}")
+        points = points.contiguous()
+        if out is None:
+            out = self._torch.empty((self.M, 3), dtype=self.real_dtype, device=self.device)
+        elif out.dtype != self.real_dtype or out.shape != (self.M, 3) or not out.is_contiguous():
+            raise ValueError("bad output tensor")
+        _check(lib().sgl_grad_points(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(points.data_ptr()),
+                                     ctypes.c_void_p(gg.data_ptr()), ctypes.c_void_p(out.data_ptr())),
+               "sgl_grad_points")
+        return out
+
     def close(self):
         if getattr(self, "_h", None):
             lib().sgl_destroy(self._h)
@@ -227,3 +247,36 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+@functools.lru_cache(maxsize=None)
+def _autograd():
+    import torch
+
+    class SGLTransform(torch.autograd.Function):
+        """f = Lambda(x) fhat for the points of `plan`, differentiable in fhat
+        (backward: sgl_adjoint) and in the point positions (backward:
+        sgl_grad_points, with the plan's rho held fixed).  The plan fixes the
+        points: after moving them, make a new plan."""
+
+        @staticmethod
+        def forward(ctx, fhat, points, plan):
+            ctx.plan = plan
+            ctx.save_for_backward(fhat, points)
+            return plan.forward(fhat.detach())
+
+        @staticmethod
+        def backward(ctx, g):
+            fhat, points = ctx.saved_tensors
+            plan = ctx.plan
+            g = g.contiguous().to(plan.complex_dtype)
+            gf = plan.adjoint(g) if ctx.needs_input_grad[0] else None
+            gx = plan.grad_points(fhat.detach(), points.detach(), g) if ctx.needs_input_grad[1] else None
+            return gf, gx, None
+
+    return SGLTransform
+
+
+def transform(fhat, points, plan):
+    """Differentiable f = Lambda(points) fhat through `plan` (torch.autograd)."""
+    return _autograd().apply(fhat, points, plan)

@@ -496,6 +496,26 @@ sgl_status sgl_nfft_adjoint(sgl_plan_t plan, const void *f_dev, void *eta_dev) {
   return nfft_adj(p, f_dev, eta_dev, p.prec == SGL_F64);
 }
 
+sgl_status sgl_grad_points(sgl_plan_t plan, const void *fhat_dev, const void *points_dev, const void *g_dev,
+                           void *grad_dev) {
+  if (check_plan(plan) != SGL_OK || !fhat_dev || !points_dev || !g_dev || !grad_dev) return SGL_E_INVAL;
+  Plan &p = plan->p;
+  if (p.flags & SGL_FLAG_EXACT_NDFT) return SGL_E_UNSUPPORTED;
+  const size_t cb = cbytes(p), rb = cb / 2;
+  const size_t nf = sgl_num_coeffs(p.B) * cb, np = (size_t)p.M * 3 * rb, ng = (size_t)p.M * cb;
+  if (overlaps(grad_dev, np, fhat_dev, nf) || overlaps(grad_dev, np, points_dev, np) ||
+      overlaps(grad_dev, np, g_dev, ng))
+    return SGL_E_INVAL;
+  // the forward grid (conversion and FFT as in sgl_forward), then the gradient gather
+  const sgl_status st = conv_fwd(p, fhat_dev, p.eta, 1);
+  if (st != SGL_OK) return st;
+  SGL_STAGE(SGL_STAGE_FFT_A, launch_fft_pass(p, p.passA, p.eta, p.bufX, 2, 1, 1, 1));
+  SGL_STAGE(SGL_STAGE_FFT_B, launch_fft_pass(p, p.passB, p.bufX, p.bufY, 1, 0, 1, 1));
+  SGL_STAGE(SGL_STAGE_FFT_C, launch_fft_pass(p, p.passC, p.bufY, p.bufX, 0, 0, 1, p.prec == SGL_F64));
+  SGL_STAGE(SGL_STAGE_GATHER, launch_grad_points(p, p.bufX, points_dev, g_dev, grad_dev));
+  return SGL_OK;
+}
+
 sgl_status sgl_forward(sgl_plan_t plan, const void *fhat_dev, void *f_dev) {
   if (check_plan(plan) != SGL_OK || !fhat_dev || !f_dev) return SGL_E_INVAL;
   Plan &p = plan->p;

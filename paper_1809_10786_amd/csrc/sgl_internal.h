@@ -149,6 +149,7 @@ hipError_t launch_point_radius(const Plan &p, const void *xyz, double *partial, 
 hipError_t launch_point_prep(Plan &p, const void *xyz, uint32_t *keys, int32_t *idx, void *unsorted);
 hipError_t launch_point_sort(Plan &p, uint32_t *keys, int32_t *idx, void *unsorted);
 hipError_t launch_conv_product(const Plan &p, int mode, const void *in, void *out);
+hipError_t launch_grad_points(const Plan &p, const void *grid, const void *xyz, const void *g, void *grad);
 hipError_t launch_conv_unfold(const Plan &p, void *eta, int eta_f64);
 hipError_t launch_conv_fold_eta(const Plan &p, const void *eta, int eta_f64);
 sgl_status build_conv_tables(Plan &p, const std::vector<long double> &kr, const std::vector<long double> &kp);

@@ -403,6 +403,95 @@ __global__ __launch_bounds__(256) void k_gather_direct(const cplx<R> *__restrict
   f[perm[k]] = cplx<R>{ar, ai};
 }
 
+// ---------------------------------------------------------------- gradient in x
+
+// For the gradient of f = Lambda fhat with respect to the point positions
+// (rho fixed): the NFFT sum f = sum_l alpha_l prod_j w(u_j - l_j) differentiates
+// through the window, d w(d) / d u = -(d / lambda) w(d), and u_j = N_j x~_j / 2 pi
+// with x~ = (2 atan2(sqrt(rho - r), sqrt(r)), theta, phi) (eq. x_tilde):
+//   d x~_0 / d x = -x / (r sqrt(r (rho - r))),
+//   d theta / d x = (x z, y z, -rxy^2) / (r^2 rxy),   d phi / d x = (-y, x, 0) / rxy^2.
+// Output: grad_ic = Re(conj(g_i) d f_i / d x_ic), the gradient of a real loss
+// whose gradient with respect to f is g (conjugate Wirtinger convention).
+// Undefined (NaN) on the z axis, at the origin and at r >= rho.
+template <class R, int Q2>
+__global__ __launch_bounds__(256) void k_grad_points(const cplx<R> *__restrict__ grid,
+                                                     const PointRec<R> *__restrict__ pts,
+                                                     const int32_t *__restrict__ perm, int64_t M, Geom g,
+                                                     double lam, double rho, const R *__restrict__ xyz,
+                                                     const cplx<R> *__restrict__ gin, R *__restrict__ grad) {
+  constexpr int q = Q2 / 2;
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= M) return;
+  const PointRec<R> pr = pts[k];
+  const int i = perm[k];
+  const int b0 = cell0(pr.cell), b1 = cell1(pr.cell), b2 = cell2(pr.cell);
+  const R inv2lam = (R)(0.5 / lam), invlam = (R)(1.0 / lam);
+  R w2[Q2], d2[Q2];
+  int i2[Q2];
+#pragma unroll
+  for (int t = 0; t < Q2; ++t) {
+    const R d = pr.frac[2] + (R)(q - 1 - t);
+    w2[t] = gauss<R>(d, inv2lam);
+    d2[t] = -d * invlam * w2[t];
+    i2[t] = stored_index(b2 - q + 1 + t, 2, g);
+  }
+  cplx<R> f0 = {0, 0}, f1 = {0, 0}, f2 = {0, 0};  // d f / d u_0, u_1, u_2
+  for (int t0 = 0; t0 < Q2; ++t0) {
+    const int s0 = stored_index(b0 - q + 1 + t0, 0, g);
+    const R e0 = pr.frac[0] + (R)(q - 1 - t0);
+    const R w0 = gauss<R>(e0, inv2lam), dw0 = -e0 * invlam * w0;
+    cplx<R> a = {0, 0}, a1 = {0, 0}, a2 = {0, 0};
+    for (int t1 = 0; t1 < Q2; ++t1) {
+      const int s1 = stored_index(b1 - q + 1 + t1, 1, g);
+      const R e1 = pr.frac[1] + (R)(q - 1 - t1);
+      const R w1 = gauss<R>(e1, inv2lam), dw1 = -e1 * invlam * w1;
+      const cplx<R> *row = grid + ((size_t)s0 * g.E[1] + s1) * g.E[2];
+      cplx<R> c = {0, 0}, cd = {0, 0};
+#pragma unroll
+      for (int t2 = 0; t2 < Q2; ++t2) {
+        const cplx<R> v = row[i2[t2]];
+        c.re += w2[t2] * v.re;
+        c.im += w2[t2] * v.im;
+        cd.re += d2[t2] * v.re;
+        cd.im += d2[t2] * v.im;
+      }
+      a.re += w1 * c.re;
+      a.im += w1 * c.im;
+      a1.re += dw1 * c.re;
+      a1.im += dw1 * c.im;
+      a2.re += w1 * cd.re;
+      a2.im += w1 * cd.im;
+    }
+    f0.re += dw0 * a.re;
+    f0.im += dw0 * a.im;
+    f1.re += w0 * a1.re;
+    f1.im += w0 * a1.im;
+    f2.re += w0 * a2.re;
+    f2.im += w0 * a2.im;
+  }
+  // chain rule in double
+  const double x = (double)xyz[3 * (size_t)i], y = (double)xyz[3 * (size_t)i + 1], z = (double)xyz[3 * (size_t)i + 2];
+  const double rxy = hypot(x, y), r = hypot(rxy, z);
+  const cplx<R> gv = gin[i];
+  // Re(conj(g) df/du_j) times du_j / d x~_j = N_j / 2 pi
+  const double inv2pi = 0.15915494309189533576888376337251436;
+  const double c0 = ((double)gv.re * f0.re + (double)gv.im * f0.im) * g.N[0] * inv2pi;
+  const double c1 = ((double)gv.re * f1.re + (double)gv.im * f1.im) * g.N[1] * inv2pi;
+  const double c2 = ((double)gv.re * f2.re + (double)gv.im * f2.im) * g.N[2] * inv2pi;
+  double gx = NAN, gy = NAN, gz = NAN;
+  if (rxy > 0.0 && r < rho) {
+    const double dt0 = -1.0 / (r * sqrt(r * (rho - r)));  // d x~_0 / d r divided by r
+    const double r2 = r * r, rxy2 = rxy * rxy;
+    gx = c0 * dt0 * x + c1 * x * z / (r2 * rxy) - c2 * y / rxy2;
+    gy = c0 * dt0 * y + c1 * y * z / (r2 * rxy) + c2 * x / rxy2;
+    gz = c0 * dt0 * z - c1 * rxy / r2;
+  }
+  grad[3 * (size_t)i] = (R)gx;
+  grad[3 * (size_t)i + 1] = (R)gy;
+  grad[3 * (size_t)i + 2] = (R)gz;
+}
+
 // ---------------------------------------------------------------- scatter
 
 // Taps t in [0, Q2) of a point with base cell b whose stored index falls in
@@ -1191,6 +1280,15 @@ __global__ __launch_bounds__(256) void k_fold_tiles8(const cplx<R> *__restrict__
   grid[cell] = cplx<double>{ar, ai};
 }
 
+template <class R, int Q2>
+hipError_t grad_q(const Plan &p, const void *grid, const void *xyz, const void *g, void *grad) {
+  const Geom gg = make_geom(p);
+  k_grad_points<R, Q2><<<(unsigned)((p.M + 255) / 256), 256, 0, p.stream>>>(
+      (const cplx<R> *)grid, (const PointRec<R> *)p.pts, p.perm, p.M, gg, p.lambda, p.rho, (const R *)xyz,
+      (const cplx<R> *)g, (R *)grad);
+  return hipGetLastError();
+}
+
 template <class R>
 hipError_t fold_r(const Plan &p, void *grid) {
   const Geom g = make_geom(p);
@@ -1244,6 +1342,14 @@ hipError_t launch_scatter(const Plan &p, const void *f, void *grid) {
     SGL_Q_CASES(scatter_q, double, p, f, grid)
   } else {
     SGL_Q_CASES(scatter_q, float, p, f, grid)
+  }
+}
+
+hipError_t launch_grad_points(const Plan &p, const void *grid, const void *xyz, const void *g, void *grad) {
+  if (p.prec == SGL_F64) {
+    SGL_Q_CASES(grad_q, double, p, grid, xyz, g, grad)
+  } else {
+    SGL_Q_CASES(grad_q, float, p, grid, xyz, g, grad)
   }
 }
 

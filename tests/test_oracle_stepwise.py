@@ -196,3 +196,50 @@ def test_nfsglft_error_decays_in_q():
     f0 = oracle.direct_forward(B, pts, fh)
     errs = [np.abs(sw.forward(B, fh, pts, q=q) - f0).max() for q in (3, 5, 7, 9)]
     assert all(errs[i + 1] < 0.2 * errs[i] for i in range(len(errs) - 1))
+
+
+# ------------------------------------------------------------ gradient in x
+
+
+def test_basis_grad_matches_central_differences():
+    """d H / d x against central differences of the basis itself (B = 4)."""
+    B = 4
+    pts = np.array([[0.3, -0.5, 0.7], [-1.1, 0.4, -0.2], [0.6, 0.9, 1.3]])
+    G = sw.sgl_basis_grad(B, pts)
+    h = 1e-6
+    for c in range(3):
+        e = np.zeros(3)
+        e[c] = h
+        fd = (sw.sgl_basis(B, pts + e) - sw.sgl_basis(B, pts - e)) / (2 * h)
+        assert np.abs(G[c] - fd).max() < 1e-7 * max(1.0, np.abs(fd).max())
+
+
+def test_basis_grad_closed_forms():
+    """H_100 is constant; H_210 = N_21 sqrt(3/(4 pi)) z; H_211 = -N_21 sqrt(3/(8 pi)) (x + i y)
+    (Condon-Shortley phase of P_lm in Rodrigues form)."""
+    pts = np.array([[0.3, -0.5, 0.7], [-1.1, 0.4, -0.2]])
+    G = sw.sgl_basis_grad(2, pts)
+    n21 = math.sqrt(2.0 / math.gamma(2.5))
+    mu100, mu210, mu211 = sw.mu_of(1, 0, 0), sw.mu_of(2, 1, 0), sw.mu_of(2, 1, 1)
+    assert np.abs(G[:, :, mu100]).max() < 1e-14
+    c = n21 * math.sqrt(3.0 / (4 * math.pi))
+    assert np.allclose(G[:, :, mu210], np.array([[0, 0], [0, 0], [c, c]]), atol=1e-13)
+    c1 = -n21 * math.sqrt(3.0 / (8 * math.pi))
+    assert np.allclose(G[:, :, mu211], np.array([[c1, c1], [1j * c1, 1j * c1], [0, 0]]), atol=1e-13)
+
+
+def test_forward_grad_matches_direct_sum_differences():
+    """Gradient of f = Lambda fhat against central differences of the exact
+    direct sum (B = 6, long double build of the oracle library)."""
+    B = 6
+    rng = np.random.default_rng(3)
+    pts = rng.standard_normal((5, 3)) * 0.7
+    fh = wl.coefficients(B, 4)
+    g = sw.forward_grad(B, pts, fh)
+    h = 1e-5
+    for c in range(3):
+        e = np.zeros(3)
+        e[c] = h
+        fd = (oracle.direct_forward(B, pts + e, fh, long_double=True)
+              - oracle.direct_forward(B, pts - e, fh, long_double=True)) / (2 * h)
+        assert np.abs(g[:, c] - fd).max() < 1e-8 * np.abs(fd).max()
