@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="b64_m4e6_f32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--grad", action="store_true",
+                    help="time the differentiation step (forward, adjoint and point gradient) instead")
     ap.add_argument("--conv-split16", action="store_true",
                     help="conversion products on the FP16 matrix cores with hi/lo split operands")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -211,6 +213,52 @@ def profiled_traffic(workload, kernel):
     return None
 
 
+def bench_grad(a, torch, wl, sgl):
+    """Differentiation step of f = Lambda(x) fhat: forward, adjoint (dL/dfhat)
+    and point gradient (dL/dx, rho fixed) per step, with the point gradient of
+    sampled points against the oracle's analytic gradient."""
+    from oracle import stepwise as sw
+
+    w, pts, fh, y = wl.workload(a.workload, seed=0)
+    B, M, q, prec = w["B"], w["M"], w["q"], w["prec"]
+    rdt = torch.float64 if prec == "f64" else torch.float32
+    cdt = torch.complex128 if prec == "f64" else torch.complex64
+    pu = pts.astype(np.float32).astype(np.float64) if prec == "f32" else pts
+    rho = 1.0001 * float(np.linalg.norm(pu, axis=1).max())
+    P = torch.from_numpy(pu).to("cuda", rdt)
+    dfh = torch.from_numpy(fh).to("cuda", cdt)
+    dy = torch.from_numpy(y).to("cuda", cdt)
+    plan = sgl.Plan(P, B, sigma=w["sigma"], q=q, rho=rho, precision=prec)
+    f = torch.empty(M, dtype=cdt, device="cuda")
+    gf = torch.empty(plan.nc, dtype=cdt, device="cuda")
+    gx = torch.empty((M, 3), dtype=rdt, device="cuda")
+    for _ in range(a.warmup):
+        plan.forward(dfh, out=f)
+        plan.adjoint(dy, out=gf)
+        plan.grad_points(dfh, P, dy, out=gx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        plan.forward(dfh, out=f)
+        plan.adjoint(dy, out=gf)
+        plan.grad_points(dfh, P, dy, out=gx)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / a.steps
+    print(f"[bench] grad {a.steps} steps: {ms:.3f} ms/step", file=sys.stderr, flush=True)
+    idx = np.sort(np.random.default_rng(5).choice(M, 40, replace=False))
+    fhu = fh.astype(np.complex64).astype(np.complex128) if prec == "f32" else fh
+    yu = y.astype(np.complex64).astype(np.complex128) if prec == "f32" else y
+    g0 = np.real(np.conj(yu[idx])[:, None] * sw.forward_grad(B, pu[idx], fhu))
+    gg = gx.cpu().numpy().astype(np.float64)[idx]
+    gerr = float(np.abs(gg - g0).max() / np.abs(g0).max())
+    print(json.dumps({
+        "metric": "points/s of the differentiation step (f, dL/dfhat, dL/dx)",
+        "value": M / (ms * 1e-3), "unit": "points/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "dtype": prec, "data": "synthetic",
+        "config": {"workload": a.workload, "B": B, "M": M, "q": q, "rho": rho},
+        "grad_points_rel_err_max": gerr, "sample_points": len(idx)}), flush=True)
+
+
 def main():
     a = parse()
     if a.summarize:
@@ -225,6 +273,8 @@ def main():
     from tests import workloads as wl
     import paper_1809_10786_amd as sgl
 
+    if a.grad:
+        return bench_grad(a, torch, wl, sgl)
     w, pts, fh, y = wl.workload(a.workload, seed=0)
     B, M, q, prec = w["B"], w["M"], w["q"], w["prec"]
     rdt = torch.float64 if prec == "f64" else torch.float32

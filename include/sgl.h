@@ -145,6 +145,23 @@ sgl_status sgl_nfft_adjoint(sgl_plan_t plan, const void *f_dev, void *eta_dev);
 sgl_status sgl_grad_points(sgl_plan_t plan, const void *fhat_dev, const void *points_dev, const void *g_dev,
                            void *grad_dev);
 
+/* Inverse transform (the iNFSGLFT of Section 8 over the normal equations of
+ * the first kind, Section 2): weighted CGNR (Golub & Van Loan, Alg. 10.4.1)
+ * for min_fhat sum_i w_i |y_i - (Lambda fhat)_i|^2, i.e.
+ * Lambda^H W Lambda fhat = Lambda^H W y.  y_dev: M complex samples (caller
+ * order); w_dev: M nonnegative reals (plan precision) or NULL for W = I
+ * (density-compensation weights act as a preconditioner); fhat_dev: Nc
+ * complex, the initial guess on entry and the solution on return.  Stops after
+ * maxiter iterations or once |Lambda^H W r| <= tol |Lambda^H W y|.  Every
+ * iteration runs one forward and one adjoint transform; vectors are in the
+ * plan's precision, all scalars in FP64.  info (host, 3 doubles, may be
+ * NULL): {iterations, |Lambda^H W r| / |Lambda^H W y|, |W^(1/2) r|}.
+ * Synchronous (the step lengths are read on the host each iteration).
+ * SGL_E_INVAL for null y/fhat, negative maxiter or tol, or fhat overlapping
+ * y or w. */
+sgl_status sgl_cgnr(sgl_plan_t plan, const void *y_dev, const void *w_dev, void *fhat_dev, int32_t maxiter,
+                    double tol, double *info);
+
 /* The rho the plan uses (host pointer out). */
 sgl_status sgl_plan_rho(sgl_plan_t plan, double *rho);
 

@@ -22,7 +22,7 @@ SYMBOLS = (
     "sgl_num_coeffs", "sgl_coeff_index", "sgl_eta_dims", "sgl_plan", "sgl_forward", "sgl_adjoint",
     "sgl_conv_forward", "sgl_conv_adjoint", "sgl_nfft_forward", "sgl_nfft_adjoint", "sgl_plan_rho",
     "sgl_plan_info", "sgl_plan_profile", "sgl_plan_stage_times", "sgl_destroy", "sgl_status_string",
-    "sgl_last_error", "sgl_grad_points",
+    "sgl_last_error", "sgl_grad_points", "sgl_cgnr",
 )
 
 STAGES = ("conv_radial", "conv_polar", "fft_A", "fft_B", "fft_C", "gather", "scatter", "fft_Ch", "fft_Bh",
@@ -71,6 +71,8 @@ def lib():
         L.sgl_status_string.argtypes, L.sgl_status_string.restype = [ctypes.c_int], ctypes.c_char_p
         L.sgl_last_error.argtypes, L.sgl_last_error.restype = [], ctypes.c_char_p
         L.sgl_grad_points.argtypes, L.sgl_grad_points.restype = [vp, vp, vp, vp, vp], ctypes.c_int
+        L.sgl_cgnr.argtypes = [vp, vp, vp, vp, i32, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]
+        L.sgl_cgnr.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -236,6 +238,25 @@ class Plan:
                                      ctypes.c_void_p(gg.data_ptr()), ctypes.c_void_p(out.data_ptr())),
                "sgl_grad_points")
         return out
+
+    def cgnr(self, y, weights=None, x0=None, maxiter=100, tol=1e-6):
+        """Weighted CGNR for min sum_i w_i |y_i - (Lambda fhat)_i|^2 (the
+        inverse transform).  Returns (fhat, info) with info = {iterations,
+        rel_normal_residual, weighted_residual_norm}; x0 defaults to zero."""
+        yy = self._in(y, self.M, "y")
+        w = None
+        if weights is not None:
+            if not weights.is_cuda or weights.dtype != self.real_dtype or weights.numel() != self.M:
+                raise ValueError(f"weights must be a CUDA {self.real_dtype} tensor with {self.M} elements")
+            w = weights.contiguous()
+        x = self._torch.zeros(self.nc, dtype=self.complex_dtype, device=self.device)
+        if x0 is not None:
+            x.copy_(self._in(x0, self.nc, "x0"))
+        info = (ctypes.c_double * 3)()
+        _check(lib().sgl_cgnr(self._h, ctypes.c_void_p(yy.data_ptr()),
+                              ctypes.c_void_p(w.data_ptr()) if w is not None else None,
+                              ctypes.c_void_p(x.data_ptr()), int(maxiter), float(tol), info), "sgl_cgnr")
+        return x, {"iterations": int(info[0]), "rel_normal_residual": info[1], "weighted_residual_norm": info[2]}
 
     def close(self):
         if getattr(self, "_h", None):

@@ -516,16 +516,39 @@ sgl_status sgl_grad_points(sgl_plan_t plan, const void *fhat_dev, const void *po
   return SGL_OK;
 }
 
+// The whole transforms without argument checks.  The fast path hands FP64 eta
+// between the conversion and the FFT in both modes.
+static sgl_status plan_forward(Plan &p, const void *fhat_dev, void *f_dev) {
+  const int eta_f64 = (p.flags & SGL_FLAG_EXACT_NDFT) ? (p.prec == SGL_F64) : 1;
+  const sgl_status st = conv_fwd(p, fhat_dev, p.eta, eta_f64);
+  if (st != SGL_OK) return st;
+  return nfft_fwd(p, p.eta, eta_f64, f_dev);
+}
+
+static sgl_status plan_adjoint(Plan &p, const void *f_dev, void *fhat_dev) {
+  const int eta_f64 = (p.flags & SGL_FLAG_EXACT_NDFT) ? (p.prec == SGL_F64) : 1;
+  const sgl_status st = nfft_adj(p, f_dev, p.eta, eta_f64);
+  if (st != SGL_OK) return st;
+  return conv_adj(p, p.eta, eta_f64, fhat_dev);
+}
+
+sgl_status sgl_cgnr(sgl_plan_t plan, const void *y_dev, const void *w_dev, void *fhat_dev, int32_t maxiter,
+                    double tol, double *info) {
+  if (check_plan(plan) != SGL_OK || !y_dev || !fhat_dev || maxiter < 0 || !(tol >= 0.0) || !std::isfinite(tol))
+    return SGL_E_INVAL;
+  Plan &p = plan->p;
+  const size_t cb = cbytes(p);
+  const size_t nf = sgl_num_coeffs(p.B) * cb, ny = (size_t)p.M * cb, nw = (size_t)p.M * (cb / 2);
+  if (overlaps(fhat_dev, nf, y_dev, ny) || (w_dev && overlaps(fhat_dev, nf, w_dev, nw))) return SGL_E_INVAL;
+  return cgnr_run(p, y_dev, w_dev, fhat_dev, maxiter, tol, info, plan_forward, plan_adjoint);
+}
+
 sgl_status sgl_forward(sgl_plan_t plan, const void *fhat_dev, void *f_dev) {
   if (check_plan(plan) != SGL_OK || !fhat_dev || !f_dev) return SGL_E_INVAL;
   Plan &p = plan->p;
   const size_t cb = cbytes(p);
   if (overlaps(fhat_dev, sgl_num_coeffs(p.B) * cb, f_dev, (size_t)p.M * cb)) return SGL_E_INVAL;
-  // the fast path hands FP64 eta from the conversion to the FFT in both modes
-  const int eta_f64 = (p.flags & SGL_FLAG_EXACT_NDFT) ? (p.prec == SGL_F64) : 1;
-  const sgl_status st = conv_fwd(p, fhat_dev, p.eta, eta_f64);
-  if (st != SGL_OK) return st;
-  return nfft_fwd(p, p.eta, eta_f64, f_dev);
+  return plan_forward(p, fhat_dev, f_dev);
 }
 
 sgl_status sgl_adjoint(sgl_plan_t plan, const void *f_dev, void *fhat_dev) {
@@ -533,11 +556,7 @@ sgl_status sgl_adjoint(sgl_plan_t plan, const void *f_dev, void *fhat_dev) {
   Plan &p = plan->p;
   const size_t cb = cbytes(p);
   if (overlaps(fhat_dev, sgl_num_coeffs(p.B) * cb, f_dev, (size_t)p.M * cb)) return SGL_E_INVAL;
-  const int exact = (p.flags & SGL_FLAG_EXACT_NDFT) != 0;
-  const int eta_f64 = exact ? (p.prec == SGL_F64) : 1;  // NFFT adjoint hands FP64 eta to the conversion
-  const sgl_status st = nfft_adj(p, f_dev, p.eta, eta_f64);
-  if (st != SGL_OK) return st;
-  return conv_adj(p, p.eta, eta_f64, fhat_dev);
+  return plan_adjoint(p, f_dev, fhat_dev);
 }
 
 sgl_status sgl_plan_rho(sgl_plan_t plan, double *rho) {

@@ -150,6 +150,10 @@ hipError_t launch_point_prep(Plan &p, const void *xyz, uint32_t *keys, int32_t *
 hipError_t launch_point_sort(Plan &p, uint32_t *keys, int32_t *idx, void *unsorted);
 hipError_t launch_conv_product(const Plan &p, int mode, const void *in, void *out);
 hipError_t launch_grad_points(const Plan &p, const void *grid, const void *xyz, const void *g, void *grad);
+// Weighted CGNR over the plan's transforms; fwd / adj: fhat -> f and f -> fhat.
+sgl_status cgnr_run(Plan &p, const void *y_dev, const void *w_dev, void *fhat_dev, int maxiter, double tol,
+                    double *info, sgl_status (*fwd)(Plan &, const void *, void *),
+                    sgl_status (*adj)(Plan &, const void *, void *));
 hipError_t launch_conv_unfold(const Plan &p, void *eta, int eta_f64);
 hipError_t launch_conv_fold_eta(const Plan &p, const void *eta, int eta_f64);
 sgl_status build_conv_tables(Plan &p, const std::vector<long double> &kr, const std::vector<long double> &kp);

@@ -107,6 +107,10 @@ def test_null_arguments():
                  "sgl_nfft_adjoint"):
         assert getattr(L, name)(None, ctypes.c_void_p(16), ctypes.c_void_p(32)) == sgl.SGL_E_INVAL
     assert L.sgl_destroy(None) == sgl.SGL_E_INVAL
+    info = (ctypes.c_double * 3)()
+    assert L.sgl_cgnr(None, ctypes.c_void_p(16), None, ctypes.c_void_p(32), 10, 1e-6, info) == sgl.SGL_E_INVAL
+    assert L.sgl_grad_points(None, ctypes.c_void_p(16), ctypes.c_void_p(32), ctypes.c_void_p(48),
+                             ctypes.c_void_p(64)) == sgl.SGL_E_INVAL
     assert L.sgl_plan_rho(None, None) == sgl.SGL_E_INVAL
     assert L.sgl_eta_dims(8, None) == sgl.SGL_E_INVAL
 
