@@ -162,6 +162,48 @@ sgl_status sgl_grad_points(sgl_plan_t plan, const void *fhat_dev, const void *po
 sgl_status sgl_cgnr(sgl_plan_t plan, const void *y_dev, const void *w_dev, void *fhat_dev, int32_t maxiter,
                     double tol, double *info);
 
+/* ---- Learned density-compensation weights for sgl_cgnr -------------------
+ * Weights w_i = exp(c_i - d_i - |x_i|^2) / M, with d_i the log point density
+ * in Cartesian cells of edge rho / 16 and c = MLP(features): a 4 -> 64 -> 64
+ * -> 1 tanh network (float32 parameters, sgl_mlp_num_params() of them:
+ * W1[64][4], b1[64], W2[64][64], b2[64], W3[64], b3).  With c = 0 (c_dev NULL)
+ * the weights are the plain histogram estimate e^{-r^2} / (M density), the
+ * quadrature weights of the e^{-r^2}-orthonormal SGL basis; the network is
+ * trained to improve on them (the training loop is in the Python binding).
+ * All calls enqueue on the plan's stream; SGL_E_INVAL for null pointers. */
+int32_t sgl_mlp_num_params(void);
+/* feat_dev: M x 4 floats {log density at cell edges rho/32, rho/16, rho/8; |x|^2 / rho^2};
+ * points_dev: the plan's M x 3 points (plan precision).  Synchronous. */
+sgl_status sgl_point_features(sgl_plan_t plan, const void *points_dev, float *feat_dev);
+/* c_dev[i] = MLP(feat_i) (M floats). */
+sgl_status sgl_mlp_forward(sgl_plan_t plan, const float *params_dev, const float *feat_dev, float *c_dev);
+/* grad_dev = d/dparams sum_i dc_i MLP(feat_i) (sgl_mlp_num_params floats);
+ * deterministic (fixed-order reduction).  Synchronous. */
+sgl_status sgl_mlp_backward(sgl_plan_t plan, const float *params_dev, const float *feat_dev, const float *dc_dev,
+                            float *grad_dev);
+/* One Adam step (Kingma & Ba) on the parameters; m_dev, v_dev: moment buffers
+ * (start at zero), step >= 1. */
+sgl_status sgl_mlp_adam(sgl_plan_t plan, float *params_dev, const float *grad_dev, float *m_dev, float *v_dev,
+                        float lr, float beta1, float beta2, float eps, int32_t step);
+/* w_dev: M weights (plan precision) from c (NULL: c = 0) and the features. */
+sgl_status sgl_mlp_weights(sgl_plan_t plan, const float *c_dev, const float *feat_dev, void *w_dev);
+/* dc_dev[i] = scale * 2 Re(y_i conj(g_i)) w_i: the gradient with respect to c of
+ * scale * |Lambda^H (w y) - fhat|^2 when g = Lambda (Lambda^H (w y) - fhat). */
+sgl_status sgl_mlp_weight_grad(sgl_plan_t plan, const void *y_dev, const void *g_dev, const void *w_dev,
+                               double scale, float *dc_dev);
+
+/* One training step (synchronous) on nbatch coefficient vectors fhat_dev
+ * (nbatch x num_coeffs, plan precision, drawn by the caller): with y = Lambda
+ * fhat_b and w from the current network, the loss is the mean over b of
+ * |Lambda^H (w y) - fhat_b|^2 / |fhat_b|^2, i.e. how far Lambda^H W Lambda is
+ * from the identity on those vectors.  Its gradient goes through the network
+ * (sgl_mlp_weight_grad, sgl_mlp_backward) into one Adam step (beta1 0.9,
+ * beta2 0.999, eps 1e-8, learning rate lr, step >= 1).  *loss: the loss
+ * before the update.  Allocates its workspace; SGL_E_INVAL for null pointers,
+ * nbatch < 1 or a zero coefficient vector. */
+sgl_status sgl_mlp_train_step(sgl_plan_t plan, float *params_dev, float *m_dev, float *v_dev, const float *feat_dev,
+                              const void *fhat_dev, int32_t nbatch, float lr, int32_t step, double *loss);
+
 /* The rho the plan uses (host pointer out). */
 sgl_status sgl_plan_rho(sgl_plan_t plan, double *rho);
 

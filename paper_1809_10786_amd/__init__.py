@@ -22,7 +22,9 @@ SYMBOLS = (
     "sgl_num_coeffs", "sgl_coeff_index", "sgl_eta_dims", "sgl_plan", "sgl_forward", "sgl_adjoint",
     "sgl_conv_forward", "sgl_conv_adjoint", "sgl_nfft_forward", "sgl_nfft_adjoint", "sgl_plan_rho",
     "sgl_plan_info", "sgl_plan_profile", "sgl_plan_stage_times", "sgl_destroy", "sgl_status_string",
-    "sgl_last_error", "sgl_grad_points", "sgl_cgnr",
+    "sgl_last_error", "sgl_grad_points", "sgl_cgnr", "sgl_mlp_num_params", "sgl_point_features",
+    "sgl_mlp_forward", "sgl_mlp_backward", "sgl_mlp_adam", "sgl_mlp_weights", "sgl_mlp_weight_grad",
+    "sgl_mlp_train_step",
 )
 
 STAGES = ("conv_radial", "conv_polar", "fft_A", "fft_B", "fft_C", "gather", "scatter", "fft_Ch", "fft_Bh",
@@ -72,6 +74,15 @@ def lib():
         L.sgl_last_error.argtypes, L.sgl_last_error.restype = [], ctypes.c_char_p
         L.sgl_grad_points.argtypes, L.sgl_grad_points.restype = [vp, vp, vp, vp, vp], ctypes.c_int
         L.sgl_cgnr.argtypes = [vp, vp, vp, vp, i32, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]
+        f32, f64 = ctypes.c_float, ctypes.c_double
+        L.sgl_mlp_num_params.argtypes, L.sgl_mlp_num_params.restype = [], i32
+        for name, args in (("sgl_point_features", [vp, vp, vp]), ("sgl_mlp_forward", [vp, vp, vp, vp]),
+                           ("sgl_mlp_backward", [vp, vp, vp, vp, vp]),
+                           ("sgl_mlp_adam", [vp, vp, vp, vp, vp, f32, f32, f32, f32, i32]),
+                           ("sgl_mlp_weights", [vp, vp, vp, vp]), ("sgl_mlp_weight_grad", [vp, vp, vp, vp, f64, vp]),
+                           ("sgl_mlp_train_step", [vp, vp, vp, vp, vp, vp, i32, f32, i32, ctypes.POINTER(f64)])):
+            fn = getattr(L, name)
+            fn.argtypes, fn.restype = args, ctypes.c_int
         L.sgl_cgnr.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -301,3 +312,83 @@ def _autograd():
 def transform(fhat, points, plan):
     """Differentiable f = Lambda(points) fhat through `plan` (torch.autograd)."""
     return _autograd().apply(fhat, points, plan)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class WeightNet:
+    """Learned density-compensation weights for ``Plan.cgnr`` (include/sgl.h):
+    w_i = exp(c_i - d_i - |x_i|^2) / M with d_i a histogram log density and
+    c = MLP(features), a 4 -> 64 -> 64 -> 1 tanh network in float32.  The last
+    layer starts at zero, so an untrained network gives the histogram weights.
+    Training (``train``) runs ``sgl_mlp_train_step``: the loss is
+    |Lambda^H W Lambda fhat - fhat|^2 / |fhat|^2 over random coefficient vectors.
+    """
+
+    def __init__(self, device=None, seed=0):
+        import torch
+
+        self._torch = torch
+        self.device = torch.device(device) if device is not None else torch.device("cuda")
+        n = int(lib().sgl_mlp_num_params())
+        g = torch.Generator().manual_seed(int(seed))
+        H, F = 64, 4
+        w1 = (torch.rand(H * F, generator=g) * 2 - 1) / F ** 0.5
+        b1 = (torch.rand(H, generator=g) * 2 - 1) / F ** 0.5
+        w2 = (torch.rand(H * H, generator=g) * 2 - 1) / H ** 0.5
+        b2 = (torch.rand(H, generator=g) * 2 - 1) / H ** 0.5
+        p = torch.cat([w1, b1, w2, b2, torch.zeros(H + 1)])
+        assert p.numel() == n
+        self.params = p.to(self.device, torch.float32)
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.step = 0
+
+    def features(self, plan, points):
+        """(M, 4) float32 features of the plan's points (the tensor the plan was made from)."""
+        if points.dtype != plan.real_dtype or points.shape != (plan.M, 3) or not points.is_cuda:
+            raise ValueError("points must be the plan's (M, 3) CUDA tensor")
+        pts = points.contiguous()
+        feat = self._torch.empty((plan.M, 4), dtype=self._torch.float32, device=plan.device)
+        _check(lib().sgl_point_features(plan._h, _ptr(pts), _ptr(feat)), "sgl_point_features")
+        return feat
+
+    def c(self, plan, feat):
+        out = self._torch.empty(plan.M, dtype=self._torch.float32, device=plan.device)
+        _check(lib().sgl_mlp_forward(plan._h, _ptr(self.params), _ptr(feat), _ptr(out)), "sgl_mlp_forward")
+        return out
+
+    def weights(self, plan, feat, learned=True):
+        """Weights in the plan's real dtype; learned=False gives the histogram weights (c = 0)."""
+        c = self.c(plan, feat) if learned else None
+        w = self._torch.empty(plan.M, dtype=plan.real_dtype, device=plan.device)
+        _check(lib().sgl_mlp_weights(plan._h, _ptr(c), _ptr(feat), _ptr(w)), "sgl_mlp_weights")
+        return w
+
+    def train_step(self, plan, feat, fhats, lr=1e-3):
+        """One Adam step on the coefficient vectors fhats (nbatch x num_coeffs); returns the loss."""
+        if fhats.dtype != plan.complex_dtype or fhats.numel() % plan.nc or not fhats.is_cuda:
+            raise ValueError("fhats must be CUDA (nbatch, num_coeffs) of the plan's complex dtype")
+        fhats = fhats.contiguous()
+        self.step += 1
+        loss = ctypes.c_double()
+        _check(lib().sgl_mlp_train_step(plan._h, _ptr(self.params), _ptr(self.m), _ptr(self.v), _ptr(feat),
+                                        _ptr(fhats), fhats.numel() // plan.nc, float(lr), self.step,
+                                        ctypes.byref(loss)), "sgl_mlp_train_step")
+        return loss.value
+
+    def train(self, plan, feat, steps=100, nbatch=4, lr=1e-3, decay=1.5, seed=0):
+        """Train on random coefficient vectors, Re and Im iid N(0, 1) times n^-decay
+        (n the first index of the coefficient); returns the losses."""
+        torch = self._torch
+        g = torch.Generator(device=plan.device).manual_seed(int(seed))
+        n = torch.arange(1, plan.B + 1, device=plan.device)
+        scale = torch.repeat_interleave(n, n * n).to(plan.real_dtype) ** (-float(decay))
+        losses = []
+        for _ in range(int(steps)):
+            re = torch.randn((nbatch, plan.nc), generator=g, device=plan.device, dtype=plan.real_dtype)
+            im = torch.randn((nbatch, plan.nc), generator=g, device=plan.device, dtype=plan.real_dtype)
+            losses.append(self.train_step(plan, feat, torch.complex(re * scale, im * scale), lr))
+        return losses

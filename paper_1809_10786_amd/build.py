@@ -28,7 +28,8 @@ FLAGS = [
 ]
 
 SOURCES = ["sgl_api.cpp", "sgl_tables.cpp", "sgl_points.hip", "sgl_conv.hip", "sgl_conv_products.hip", "sgl_fft.hip",
-           "sgl_spread.hip", "sgl_solve.hip"]
+           "sgl_spread.hip", "sgl_solve.hip",
+           "sgl_learn.hip"]
 
 
 def _compile(src, verbose):

@@ -543,6 +543,123 @@ sgl_status sgl_cgnr(sgl_plan_t plan, const void *y_dev, const void *w_dev, void 
   return cgnr_run(p, y_dev, w_dev, fhat_dev, maxiter, tol, info, plan_forward, plan_adjoint);
 }
 
+// ---------------------------------------------------------------- learned weights
+
+int32_t sgl_mlp_num_params(void) { return mlp_num_params(); }
+
+sgl_status sgl_point_features(sgl_plan_t plan, const void *points_dev, float *feat_dev) {
+  if (check_plan(plan) != SGL_OK || !points_dev || !feat_dev) return SGL_E_INVAL;
+  return from_hip(launch_point_features(plan->p, points_dev, feat_dev));
+}
+
+sgl_status sgl_mlp_forward(sgl_plan_t plan, const float *params_dev, const float *feat_dev, float *c_dev) {
+  if (check_plan(plan) != SGL_OK || !params_dev || !feat_dev || !c_dev) return SGL_E_INVAL;
+  return from_hip(launch_mlp_forward(params_dev, feat_dev, plan->p.M, c_dev, plan->p.stream));
+}
+
+sgl_status sgl_mlp_backward(sgl_plan_t plan, const float *params_dev, const float *feat_dev, const float *dc_dev,
+                            float *grad_dev) {
+  if (check_plan(plan) != SGL_OK || !params_dev || !feat_dev || !dc_dev || !grad_dev) return SGL_E_INVAL;
+  return from_hip(launch_mlp_backward(params_dev, feat_dev, dc_dev, plan->p.M, grad_dev, plan->p.stream));
+}
+
+sgl_status sgl_mlp_adam(sgl_plan_t plan, float *params_dev, const float *grad_dev, float *m_dev, float *v_dev,
+                        float lr, float beta1, float beta2, float eps, int32_t step) {
+  if (check_plan(plan) != SGL_OK || !params_dev || !grad_dev || !m_dev || !v_dev || step < 1 || !(lr > 0.0f) ||
+      !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
+    return SGL_E_INVAL;
+  return from_hip(launch_adam(params_dev, grad_dev, m_dev, v_dev, mlp_num_params(), lr, beta1, beta2, eps, step,
+                              plan->p.stream));
+}
+
+sgl_status sgl_mlp_weights(sgl_plan_t plan, const float *c_dev, const float *feat_dev, void *w_dev) {
+  if (check_plan(plan) != SGL_OK || !feat_dev || !w_dev) return SGL_E_INVAL;
+  return from_hip(launch_mlp_weights(plan->p, c_dev, feat_dev, w_dev));
+}
+
+sgl_status sgl_mlp_weight_grad(sgl_plan_t plan, const void *y_dev, const void *g_dev, const void *w_dev,
+                               double scale, float *dc_dev) {
+  if (check_plan(plan) != SGL_OK || !y_dev || !g_dev || !w_dev || !dc_dev || !std::isfinite(scale))
+    return SGL_E_INVAL;
+  return from_hip(launch_weight_grad(plan->p, y_dev, g_dev, w_dev, scale, false, dc_dev));
+}
+
+// One training step of the weight network on coefficient vectors drawn by the
+// caller: y = Lambda fhat_b, w = weights(MLP(feat)), e_b = Lambda^H (w y) - fhat_b,
+// loss = mean_b |e_b|^2 / |fhat_b|^2; dL/dc from g = Lambda e_b; backward; Adam.
+struct TrainLayout {  // byte offsets into the training workspace, each 256-aligned
+  size_t y, t, e, w, c, dc, grad, norms, bytes;
+  explicit TrainLayout(const Plan &p) {
+    const size_t M = (size_t)p.M, nc = (size_t)sgl_num_coeffs(p.B), cb = cbytes(p);
+    size_t o = 0;
+    auto take = [&o](size_t n) {
+      const size_t at = o;
+      o += (n + 255) & ~(size_t)255;
+      return at;
+    };
+    y = take(M * cb);
+    t = take(M * cb);
+    e = take(nc * cb);
+    w = take(M * cb / 2);
+    c = take(M * sizeof(float));
+    dc = take(M * sizeof(float));
+    grad = take((size_t)mlp_num_params() * sizeof(float));
+    norms = take(2 * sizeof(double));
+    bytes = o;
+  }
+};
+
+static sgl_status train_step(Plan &p, float *params, float *m, float *v, const float *feat, const char *fhat,
+                             int nbatch, float lr, int step, double *loss, char *ws) {
+  const int64_t M = p.M, nc = sgl_num_coeffs(p.B);
+  const size_t cb = cbytes(p);
+  const TrainLayout L(p);
+  char *y = ws + L.y, *t = ws + L.t, *e = ws + L.e, *w = ws + L.w;
+  float *c = (float *)(ws + L.c), *dc = (float *)(ws + L.dc), *grad = (float *)(ws + L.grad);
+  double *norms = (double *)(ws + L.norms);
+  hipStream_t s = p.stream;
+  SGL_TRY(launch_mlp_forward(params, feat, M, c, s));
+  SGL_TRY(launch_mlp_weights(p, c, feat, w));
+  double total = 0.0;
+  for (int b = 0; b < nbatch; ++b) {
+    const char *fh = fhat + (size_t)b * nc * cb;
+    sgl_status st = plan_forward(p, fh, y);
+    if (st != SGL_OK) return st;
+    SGL_TRY(launch_scale_by(p, t, y, w, M));
+    if ((st = plan_adjoint(p, t, e)) != SGL_OK) return st;
+    SGL_TRY(launch_sub_from(p, e, fh, nc));
+    SGL_TRY(launch_norm2(p, e, nc, norms));
+    SGL_TRY(launch_norm2(p, fh, nc, norms + 1));
+    double hn[2];
+    SGL_TRY(hipMemcpyAsync(hn, norms, sizeof hn, hipMemcpyDeviceToHost, s));
+    SGL_TRY(hipStreamSynchronize(s));
+    if (!(hn[1] > 0.0)) return SGL_E_INVAL;  // a zero coefficient vector
+    total += hn[0] / hn[1];
+    if ((st = plan_forward(p, e, t)) != SGL_OK) return st;
+    SGL_TRY(launch_weight_grad(p, y, t, w, 1.0 / (nbatch * hn[1]), b > 0, dc));
+  }
+  SGL_TRY(launch_mlp_backward(params, feat, dc, M, grad, s));
+  SGL_TRY(launch_adam(params, grad, m, v, mlp_num_params(), lr, 0.9f, 0.999f, 1e-8f, step, s));
+  SGL_TRY(hipStreamSynchronize(s));
+  *loss = total / nbatch;
+  return SGL_OK;
+}
+
+sgl_status sgl_mlp_train_step(sgl_plan_t plan, float *params_dev, float *m_dev, float *v_dev, const float *feat_dev,
+                              const void *fhat_dev, int32_t nbatch, float lr, int32_t step, double *loss) {
+  if (check_plan(plan) != SGL_OK || !params_dev || !m_dev || !v_dev || !feat_dev || !fhat_dev || !loss ||
+      nbatch < 1 || step < 1 || !(lr > 0.0f))
+    return SGL_E_INVAL;
+  Plan &p = plan->p;
+  void *ws = nullptr;
+  if (hipMalloc(&ws, TrainLayout(p).bytes) != hipSuccess) return SGL_E_NOMEM;
+  const sgl_status st = train_step(p, params_dev, m_dev, v_dev, feat_dev, (const char *)fhat_dev, nbatch, lr, step,
+                                   loss, (char *)ws);
+  hipStreamSynchronize(p.stream);
+  hipFree(ws);
+  return st;
+}
+
 sgl_status sgl_forward(sgl_plan_t plan, const void *fhat_dev, void *f_dev) {
   if (check_plan(plan) != SGL_OK || !fhat_dev || !f_dev) return SGL_E_INVAL;
   Plan &p = plan->p;

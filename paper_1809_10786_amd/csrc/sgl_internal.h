@@ -150,6 +150,20 @@ hipError_t launch_point_prep(Plan &p, const void *xyz, uint32_t *keys, int32_t *
 hipError_t launch_point_sort(Plan &p, uint32_t *keys, int32_t *idx, void *unsorted);
 hipError_t launch_conv_product(const Plan &p, int mode, const void *in, void *out);
 hipError_t launch_grad_points(const Plan &p, const void *grid, const void *xyz, const void *g, void *grad);
+// Learned density-compensation weights (sgl_learn.hip).
+int mlp_num_params();
+hipError_t launch_point_features(const Plan &p, const void *xyz, float *feat);
+hipError_t launch_mlp_forward(const float *params, const float *feat, int64_t M, float *c, hipStream_t s);
+hipError_t launch_mlp_backward(const float *params, const float *feat, const float *dc, int64_t M, float *grad,
+                               hipStream_t s);
+hipError_t launch_adam(float *params, const float *grad, float *m, float *v, int n, float lr, float b1, float b2,
+                       float eps, int step, hipStream_t s);
+hipError_t launch_mlp_weights(const Plan &p, const float *c, const float *feat, void *w);
+hipError_t launch_weight_grad(const Plan &p, const void *y, const void *g, const void *w, double scale,
+                              bool accumulate, float *dc);
+hipError_t launch_scale_by(const Plan &p, void *out, const void *a, const void *w, int64_t n);
+hipError_t launch_sub_from(const Plan &p, void *a, const void *b, int64_t n);
+hipError_t launch_norm2(const Plan &p, const void *a, int64_t n, double *out_dev);
 // Weighted CGNR over the plan's transforms; fwd / adj: fhat -> f and f -> fhat.
 sgl_status cgnr_run(Plan &p, const void *y_dev, const void *w_dev, void *fhat_dev, int maxiter, double tol,
                     double *info, sgl_status (*fwd)(Plan &, const void *, void *),

@@ -111,6 +111,16 @@ def test_null_arguments():
     assert L.sgl_cgnr(None, ctypes.c_void_p(16), None, ctypes.c_void_p(32), 10, 1e-6, info) == sgl.SGL_E_INVAL
     assert L.sgl_grad_points(None, ctypes.c_void_p(16), ctypes.c_void_p(32), ctypes.c_void_p(48),
                              ctypes.c_void_p(64)) == sgl.SGL_E_INVAL
+    v = ctypes.c_void_p(16)
+    assert L.sgl_mlp_num_params() == 4 * 64 + 64 + 64 * 64 + 64 + 64 + 1
+    assert L.sgl_point_features(None, v, v) == sgl.SGL_E_INVAL
+    assert L.sgl_mlp_forward(None, v, v, v) == sgl.SGL_E_INVAL
+    assert L.sgl_mlp_backward(None, v, v, v, v) == sgl.SGL_E_INVAL
+    assert L.sgl_mlp_adam(None, v, v, v, v, 1e-3, 0.9, 0.999, 1e-8, 1) == sgl.SGL_E_INVAL
+    assert L.sgl_mlp_weights(None, None, v, v) == sgl.SGL_E_INVAL
+    assert L.sgl_mlp_weight_grad(None, v, v, v, 1.0, v) == sgl.SGL_E_INVAL
+    loss = ctypes.c_double()
+    assert L.sgl_mlp_train_step(None, v, v, v, v, v, 1, 1e-3, 1, ctypes.byref(loss)) == sgl.SGL_E_INVAL
     assert L.sgl_plan_rho(None, None) == sgl.SGL_E_INVAL
     assert L.sgl_eta_dims(8, None) == sgl.SGL_E_INVAL
 

@@ -1,0 +1,241 @@
+"""Learned density-compensation weights: every kernel against the oracle
+(oracle/learn.py), the native training step against the oracle's loss,
+gradient and Adam step, and the weights as the preconditioner of CGNR on a
+clustered cloud (B = 32, M = 3e5, eight Gaussian clusters with Dirichlet(1)
+weights, 1 % noise) with plain CGNR (W = I) as the judge of the error.
+
+Tolerances: feature counts are compared exactly (both sides decide the cell
+in FP64 from the same coordinates); the network runs in FP32 on the GPU, so
+its output is compared at 1e-5 (1 + |c|), parameter gradients at 1e-4 of the
+largest entry, and the loss, which sees the FP32 network through the weights,
+at 1e-5 relative.
+"""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import learn as ol
+from tests import workloads as wl
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def dev(x, dtype):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(device="cuda", dtype=dtype)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def random_params(seed, scale=0.5):
+    return np.random.default_rng(seed).uniform(-scale, scale, ol.num_params()).astype(np.float32)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_features_match_oracle(prec):
+    import paper_1809_10786_amd as sgl
+
+    M = 50_001
+    pts = wl.clustered_points(M, 300)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    P = dev(pts, dt)
+    pu = host(P).astype(np.float64)
+    say(f"features {prec} M={M}")
+    plan = sgl.Plan(P, 6, precision=prec)
+    net = sgl.WeightNet(seed=0)
+    f = host(net.features(plan, P)).astype(np.float64)
+    ref = ol.features(pu, plan.rho)
+    for s, n in enumerate(ol.GRIDS):
+        h = 2 * plan.rho / n
+        cg = np.rint(np.exp(f[:, s]) * M * h ** 3)
+        cr = np.rint(np.exp(ref[:, s]) * M * h ** 3)
+        assert np.array_equal(cg, cr), f"grid {n}: {np.sum(cg != cr)} counts differ"
+    assert np.allclose(f, ref, rtol=2e-6, atol=2e-6)
+    plan.close()
+
+
+@pytest.mark.parametrize("M", [1, 10_000])
+def test_mlp_forward_backward_adam_match_oracle(M):
+    import paper_1809_10786_amd as sgl
+
+    rng = np.random.default_rng(M)
+    pts = wl.gaussian_points(max(M, 2), 301)[:M]
+    say(f"mlp M={M}")
+    plan = sgl.Plan(dev(pts, torch.float64), 4)
+    net = sgl.WeightNet(seed=1)
+    p = random_params(2)
+    net.params.copy_(dev(p, torch.float32))
+    feat = rng.standard_normal((M, 4)).astype(np.float32) * 2
+    F = dev(feat, torch.float32)
+    c = host(net.c(plan, F)).astype(np.float64)
+    cref = ol.mlp(p.astype(np.float64), feat.astype(np.float64))
+    assert np.all(np.abs(c - cref) <= 1e-5 * (1 + np.abs(cref))), np.max(np.abs(c - cref))
+    dc = rng.standard_normal(M).astype(np.float32)
+    DC = dev(dc, torch.float32)
+    grad = torch.empty(ol.num_params(), dtype=torch.float32, device="cuda")
+    sgl._check(sgl.lib().sgl_mlp_backward(plan._h, sgl._ptr(net.params), sgl._ptr(F), sgl._ptr(DC), sgl._ptr(grad)),
+               "sgl_mlp_backward")
+    g = host(grad).astype(np.float64)
+    gref = ol.mlp_grad(p.astype(np.float64), feat.astype(np.float64), dc.astype(np.float64))
+    assert np.max(np.abs(g - gref)) <= 1e-4 * np.max(np.abs(gref)), np.max(np.abs(g - gref))
+    # three Adam steps on that gradient
+    pr, mr, vr = p.astype(np.float64), np.zeros(len(p)), np.zeros(len(p))
+    m = torch.zeros_like(net.params)
+    v = torch.zeros_like(net.params)
+    for step in (1, 2, 3):
+        sgl._check(sgl.lib().sgl_mlp_adam(plan._h, sgl._ptr(net.params), sgl._ptr(grad), sgl._ptr(m), sgl._ptr(v),
+                                          1e-2, 0.9, 0.999, 1e-8, step), "sgl_mlp_adam")
+        pr, mr, vr = ol.adam(pr, g, mr, vr, 1e-2, step)
+    assert np.allclose(host(net.params), pr, rtol=1e-5, atol=1e-6)
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_weights_and_weight_gradient_match_oracle(prec):
+    import paper_1809_10786_amd as sgl
+
+    M = 20_000
+    rng = np.random.default_rng(7)
+    pts = wl.clustered_points(M, 302)
+    rt, ct = (torch.float64, torch.complex128) if prec == "f64" else (torch.float32, torch.complex64)
+    P = dev(pts, rt)
+    say(f"weights {prec}")
+    plan = sgl.Plan(P, 6, precision=prec)
+    net = sgl.WeightNet(seed=2)
+    F = net.features(plan, P)
+    feat = host(F).astype(np.float64)
+    c = (rng.standard_normal(M) * 0.3).astype(np.float32)
+    C = dev(c, torch.float32)
+    w = torch.empty(M, dtype=rt, device="cuda")
+    sgl._check(sgl.lib().sgl_mlp_weights(plan._h, sgl._ptr(C), sgl._ptr(F), sgl._ptr(w)), "sgl_mlp_weights")
+    wref = ol.weights(c.astype(np.float64), feat, plan.rho)
+    tol = 1e-13 if prec == "f64" else 1e-6
+    assert np.allclose(host(w), wref, rtol=tol, atol=0)
+    # c = NULL gives the histogram weights
+    w0 = net.weights(plan, F, learned=False)
+    assert np.allclose(host(w0), ol.weights(np.zeros(M), feat, plan.rho), rtol=tol, atol=0)
+    y = rng.standard_normal(M) + 1j * rng.standard_normal(M)
+    g = rng.standard_normal(M) + 1j * rng.standard_normal(M)
+    dc = torch.empty(M, dtype=torch.float32, device="cuda")
+    Y, G = dev(y, ct), dev(g, ct)  # held: a freed block would be handed to the next tensor
+    sgl._check(sgl.lib().sgl_mlp_weight_grad(plan._h, sgl._ptr(Y), sgl._ptr(G), sgl._ptr(w), 0.25, sgl._ptr(dc)),
+               "sgl_mlp_weight_grad")
+    yu, gu, wu = host(Y), host(G), host(w).astype(np.float64)
+    dref = 0.25 * 2 * np.real(yu * np.conj(gu)) * wu
+    assert np.allclose(host(dc), dref, rtol=1e-6, atol=1e-6 * np.max(np.abs(dref)))
+    plan.close()
+
+
+def test_train_step_matches_oracle():
+    import paper_1809_10786_amd as sgl
+
+    B, M = 6, 3_001
+    rng = np.random.default_rng(8)
+    pts = wl.gaussian_points(M, 303) * 0.8
+    P = dev(pts, torch.float64)
+    say("train step B=6 M=3001")
+    plan = sgl.Plan(P, B, q=12)
+    net = sgl.WeightNet(seed=3)
+    p = random_params(4, scale=0.3)
+    net.params.copy_(dev(p, torch.float32))
+    F = net.features(plan, P)
+    feat = host(F).astype(np.float64)
+    nc = oracle.num_coeffs(B)
+    fh = rng.standard_normal((2, nc)) + 1j * rng.standard_normal((2, nc))
+    loss = net.train_step(plan, F, dev(fh, torch.complex128), lr=1e-3)
+    p_after = host(net.params).astype(np.float64)
+    # oracle: the same step with the direct sums
+    pd = p.astype(np.float64)
+    c = ol.mlp(pd, feat)
+    w = ol.weights(c, feat, plan.rho)
+    Lr, dc = ol.loss_and_dc(lambda f: oracle.direct_forward(B, pts, f), lambda y: oracle.direct_adjoint(B, pts, y),
+                            w, list(fh))
+    g = ol.mlp_grad(pd, feat, dc)
+    pr, _, _ = ol.adam(pd, g, np.zeros_like(pd), np.zeros_like(pd), 1e-3, 1)
+    say(f"loss gpu {loss:.10g} oracle {Lr:.10g}")
+    assert abs(loss - Lr) <= 1e-5 * Lr
+    big = np.abs(g) > 1e-3 * np.max(np.abs(g))
+    dg, dr = p_after - pd, pr - pd
+    assert np.all(np.abs(dg[big] - dr[big]) <= 1e-6 + 1e-7 * np.abs(pd[big]))
+    assert np.all(np.abs(dg) <= 1e-3 * 1.0001 + 1e-7 * np.abs(pd))
+    plan.close()
+
+
+def loss_of(plan, w, fhats):
+    tot = 0.0
+    for fh in fhats:
+        e = plan.adjoint(w.to(plan.complex_dtype) * plan.forward(fh)) - fh
+        tot += float(torch.linalg.vector_norm(e) ** 2 / torch.linalg.vector_norm(fh) ** 2)
+    return tot / len(fhats)
+
+
+def test_learned_weights_precondition_cgnr_on_clustered_cloud():
+    """B = 32, M = 3e5 clustered points, 1 % noise.  The clusters sample r <= 3
+    only, while the weighted basis reaches r of about sqrt(4 B), so the problem
+    is ill-posed and no variant reaches a normal residual of 1e-6 within a few
+    thousand iterations; the comparison is made at 1e-3, where plain CGNR judges
+    the error of the weighted solutions."""
+    import paper_1809_10786_amd as sgl
+
+    B, M = 32, 300_000
+    say(f"clustered CGNR B={B} M={M}")
+    # train on one cloud, evaluate on another from the same distribution
+    Pt = dev(wl.clustered_points(M, 310), torch.float64)
+    Pe = dev(wl.clustered_points(M, 311), torch.float64)
+    plan_t = sgl.Plan(Pt, B)
+    net = sgl.WeightNet(seed=4)
+    Ft = net.features(plan_t, Pt)
+    t0 = time.perf_counter()
+    losses = net.train(plan_t, Ft, steps=150, nbatch=2, lr=1e-2, decay=1.5, seed=5)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    say(f"train 150 steps {t_train:.2f} s: loss {losses[0]:.4g} -> {np.mean(losses[-10:]):.4g}")
+    plan_t.close()
+
+    plan = sgl.Plan(Pe, B)
+    Fe = net.features(plan, Pe)
+    g = torch.Generator(device="cuda").manual_seed(6)
+    n = torch.arange(1, B + 1, device="cuda")
+    scale = torch.repeat_interleave(n, n * n).double() ** -1.5
+    fhats = [torch.complex(torch.randn(plan.nc, generator=g, device="cuda", dtype=torch.float64),
+                           torch.randn(plan.nc, generator=g, device="cuda", dtype=torch.float64)) * scale
+             for _ in range(3)]
+    w_hist = net.weights(plan, Fe, learned=False)
+    w_net = net.weights(plan, Fe)
+    l_hist, l_net = loss_of(plan, w_hist, fhats), loss_of(plan, w_net, fhats)
+    say(f"held-out loss: histogram {l_hist:.4g}, learned {l_net:.4g}")
+    assert l_net < 0.995 * l_hist
+
+    fstar = dev(wl.coefficients(B, 312), torch.complex128)
+    y = plan.forward(fstar)
+    rms = torch.sqrt(torch.mean(torch.abs(y) ** 2))
+    gn = torch.Generator(device="cuda").manual_seed(7)
+    noise = torch.complex(torch.randn(M, generator=gn, device="cuda", dtype=torch.float64),
+                          torch.randn(M, generator=gn, device="cuda", dtype=torch.float64)) * (0.01 * rms / 2 ** 0.5)
+    y = y + noise
+    res = {}
+    for name, w in (("plain", None), ("histogram", w_hist), ("learned", w_net)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, info = plan.cgnr(y, weights=w, maxiter=2000, tol=1e-3)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        err = float(torch.linalg.vector_norm(x - fstar) / torch.linalg.vector_norm(fstar))
+        res[name] = (info["iterations"], dt, err, info["rel_normal_residual"])
+        say(f"  {name:9s} iterations {info['iterations']:5d} time {dt:.3f} s error vs truth {err:.4g} "
+            f"normal residual {info['rel_normal_residual']:.3g}")
+    for name in res:
+        assert res[name][3] <= 1e-3, name
+    assert res["learned"][0] <= 0.75 * res["plain"][0] and res["histogram"][0] <= 0.75 * res["plain"][0]
+    # plain CGNR judges the error of the weighted solutions
+    assert res["learned"][2] <= 1.05 * res["plain"][2]
+    plan.close()
