@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--grad", action="store_true",
                     help="time the differentiation step (forward, adjoint and point gradient) instead")
+    ap.add_argument("--inverse", action="store_true",
+                    help="time the inverse transform (CGNR, plain / histogram / learned weights) instead")
     ap.add_argument("--conv-split16", action="store_true",
                     help="conversion products on the FP16 matrix cores with hi/lo split operands")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -259,6 +261,58 @@ def bench_grad(a, torch, wl, sgl):
         "grad_points_rel_err_max": gerr, "sample_points": len(idx)}), flush=True)
 
 
+def bench_inverse(a, torch, wl, sgl):
+    """Inverse transform: CGNR to a normal residual of 1e-3 on noisy samples
+    (1 % noise) with W = I, with histogram density weights and with learned
+    weights (network trained on another cloud of the same distribution)."""
+    name = a.workload if a.workload != "b64_m4e6_f32" else "b32_m3e5_clustered_f64"
+    w, pts, fh, _ = wl.workload(name, seed=0)
+    B, M, q, prec = w["B"], w["M"], w["q"], w["prec"]
+    rdt = torch.float64 if prec == "f64" else torch.float32
+    cdt = torch.complex128 if prec == "f64" else torch.complex64
+    Pt = torch.from_numpy(wl.make_points(w["points"], M, 1)).to("cuda", rdt)
+    P = torch.from_numpy(pts).to("cuda", rdt)
+    plan_t = sgl.Plan(Pt, B, sigma=w["sigma"], q=q, precision=prec)
+    net = sgl.WeightNet(seed=4)
+    Ft = net.features(plan_t, Pt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    steps = 150
+    losses = net.train(plan_t, Ft, steps=steps, nbatch=2, lr=1e-2, decay=w["decay"], seed=5)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    plan_t.close()
+    print(f"[bench] inverse: trained {steps} steps in {train_s:.2f} s, loss {losses[0]:.4g} -> {losses[-1]:.4g}",
+          file=sys.stderr, flush=True)
+    plan = sgl.Plan(P, B, sigma=w["sigma"], q=q, precision=prec)
+    F = net.features(plan, P)
+    fstar = torch.from_numpy(fh).to("cuda", cdt)
+    y = plan.forward(fstar)
+    rms = torch.sqrt(torch.mean(torch.abs(y) ** 2))
+    g = torch.Generator(device="cuda").manual_seed(7)
+    y = y + torch.complex(torch.randn(M, generator=g, device="cuda", dtype=rdt),
+                          torch.randn(M, generator=g, device="cuda", dtype=rdt)) * (0.01 * rms / 2 ** 0.5)
+    out = {}
+    for label, wt in (("plain", None), ("histogram", net.weights(plan, F, learned=False)),
+                      ("learned", net.weights(plan, F))):
+        plan.cgnr(y, weights=wt, maxiter=5, tol=1e-3)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, info = plan.cgnr(y, weights=wt, maxiter=5000, tol=1e-3)
+        torch.cuda.synchronize()
+        s = time.perf_counter() - t0
+        err = float(torch.linalg.vector_norm(x - fstar) / torch.linalg.vector_norm(fstar))
+        out[label] = {"iterations": info["iterations"], "seconds": s,
+                      "ms_per_iteration": s * 1e3 / max(info["iterations"], 1), "rel_error_vs_truth": err,
+                      "rel_normal_residual": info["rel_normal_residual"]}
+        print(f"[bench] inverse {label}: {out[label]}", file=sys.stderr, flush=True)
+    print(json.dumps({
+        "metric": "CGNR seconds to normal residual 1e-3 (learned weights)", "value": out["learned"]["seconds"],
+        "unit": "s", "n_gpus": 1, "higher_is_better": False, "dtype": prec, "data": "synthetic",
+        "config": {"workload": name, "B": B, "M": M, "q": q, "noise": 0.01, "train_steps": steps,
+                   "train_seconds": train_s}, "solves": out}), flush=True)
+
+
 def main():
     a = parse()
     if a.summarize:
@@ -275,6 +329,8 @@ def main():
 
     if a.grad:
         return bench_grad(a, torch, wl, sgl)
+    if a.inverse:
+        return bench_inverse(a, torch, wl, sgl)
     w, pts, fh, y = wl.workload(a.workload, seed=0)
     B, M, q, prec = w["B"], w["M"], w["q"], w["prec"]
     rdt = torch.float64 if prec == "f64" else torch.float32
