@@ -42,6 +42,8 @@ def parse():
                     help="time the differentiation step (forward, adjoint and point gradient) instead")
     ap.add_argument("--inverse", action="store_true",
                     help="time the inverse transform (CGNR, plain / histogram / learned weights) instead")
+    ap.add_argument("--batch", action="store_true",
+                    help="time 64 heterogeneous transforms (forward + adjoint) eagerly and as one HIP graph")
     ap.add_argument("--conv-split16", action="store_true",
                     help="conversion products on the FP16 matrix cores with hi/lo split operands")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -313,6 +315,57 @@ def bench_inverse(a, torch, wl, sgl):
                    "train_seconds": train_s}, "solves": out}), flush=True)
 
 
+def bench_batch(a, torch, wl, sgl):
+    """64 transforms, B uniform over the supported bandwidths in [16, 64], M
+    log-uniform in [1e5, 2e6], mixed points, FP32, coefficients with n^-1 decay:
+    forward + adjoint of all of them per step, eagerly (one plan after another
+    on one stream) and replayed as one HIP graph over 4 branches."""
+    specs = wl.batch_specs(64, seed=0)
+    total = sum(m for _, m in specs)
+    plans, fh, ys, outs, ghs = [], [], [], [], []
+    t0 = time.perf_counter()
+    for k, (B, M) in enumerate(specs):
+        P = torch.from_numpy(wl.mixed_points(M, 1000 + k)).to("cuda", torch.float32)
+        plans.append(sgl.Plan(P, B, precision="f32"))
+        del P
+        fh.append(torch.from_numpy(wl.coefficients(B, 2000 + k, decay=1.0)).to("cuda", torch.complex64))
+        ys.append(torch.from_numpy(wl.samples(M, 3000 + k)).to("cuda", torch.complex64))
+        outs.append(torch.empty(M, dtype=torch.complex64, device="cuda"))
+        ghs.append(torch.empty(plans[-1].nc, dtype=torch.complex64, device="cuda"))
+    torch.cuda.synchronize()
+    print(f"[bench] batch: {len(specs)} plans, {total} points, planned in {time.perf_counter() - t0:.1f} s",
+          file=sys.stderr, flush=True)
+
+    def eager():
+        for p, f, o, y, g in zip(plans, fh, outs, ys, ghs):
+            p.forward(f, out=o)
+            p.adjoint(y, out=g)
+
+    t0 = time.perf_counter()
+    b = sgl.Batch(plans, fh, outs, ys, ghs, nstreams=4)
+    capture_ms = (time.perf_counter() - t0) * 1e3
+    res = {}
+    for label, fn in (("eager", eager), ("graph", b.run)):
+        for _ in range(a.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            fn()
+        torch.cuda.synchronize()
+        res[label] = (time.perf_counter() - t0) * 1e3 / a.steps
+        print(f"[bench] batch {label}: {res[label]:.3f} ms/step", file=sys.stderr, flush=True)
+    b.close()
+    ms = res["graph"]
+    print(json.dumps({
+        "metric": "scattered points/s fwd+adj over a batch of 64 heterogeneous transforms", "value": total / (ms * 1e-3),
+        "unit": "points/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "64 transforms, B in [16, 64], M log-uniform in [1e5, 2e6], mixed points",
+                   "total_points": total, "nstreams": 4, "capture_ms": capture_ms},
+        "eager_ms_per_step": res["eager"], "graph_ms_per_step": ms}), flush=True)
+
+
 def main():
     a = parse()
     if a.summarize:
@@ -331,6 +384,8 @@ def main():
         return bench_grad(a, torch, wl, sgl)
     if a.inverse:
         return bench_inverse(a, torch, wl, sgl)
+    if a.batch:
+        return bench_batch(a, torch, wl, sgl)
     w, pts, fh, y = wl.workload(a.workload, seed=0)
     B, M, q, prec = w["B"], w["M"], w["q"], w["prec"]
     rdt = torch.float64 if prec == "f64" else torch.float32

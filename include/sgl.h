@@ -162,6 +162,32 @@ sgl_status sgl_grad_points(sgl_plan_t plan, const void *fhat_dev, const void *po
 sgl_status sgl_cgnr(sgl_plan_t plan, const void *y_dev, const void *w_dev, void *fhat_dev, int32_t maxiter,
                     double tol, double *info);
 
+/* ---- Batches of transforms -------------------------------------------------
+ * A batch records the forward (fhat_dev[j] -> f_dev[j]) and/or the adjoint
+ * (y_dev[j] -> ghat_dev[j]) of n plans (any mix of B, M and precision) once,
+ * as one HIP graph whose plans run on nstreams (1..16) concurrent branches
+ * (plan j on branch j mod nstreams); sgl_batch_run replays the whole graph with
+ * one launch on `stream`.  Each result equals that plan's own sgl_forward /
+ * sgl_adjoint on the same buffers, so a batch runs many transforms
+ * of the same shapes with no host work between them.
+ *   - the pointer arrays are read at creation: the graph keeps the device
+ *     addresses, so later runs read whatever those buffers then hold;
+ *   - pass NULL for both fhat_dev and f_dev (or y_dev and ghat_dev) to leave
+ *     that direction out; not both;
+ *   - the plans must be distinct, on the current device, with profiling off,
+ *     and must outlive the batch; while a batch runs, do not use its plans
+ *     (they share workspace with it);
+ *   - output buffers of different plans must not overlap.
+ * sgl_batch_create returns SGL_E_INVAL for a violated rule before any device
+ * work, and SGL_E_DEVICE if the capture fails.  sgl_batch_destroy waits for
+ * `stream` first. */
+typedef struct sgl_batch_s *sgl_batch_t;
+sgl_status sgl_batch_create(sgl_batch_t *out, const sgl_plan_t *plans, int32_t n, const void *const *fhat_dev,
+                            void *const *f_dev, const void *const *y_dev, void *const *ghat_dev, int32_t nstreams,
+                            void *stream);
+sgl_status sgl_batch_run(sgl_batch_t batch);
+sgl_status sgl_batch_destroy(sgl_batch_t batch);
+
 /* ---- Learned density-compensation weights for sgl_cgnr -------------------
  * Weights w_i = exp(c_i - d_i - |x_i|^2) / M, with d_i the log point density
  * in Cartesian cells of edge rho / 16 and c = MLP(features): a 4 -> 64 -> 64

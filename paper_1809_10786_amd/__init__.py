@@ -24,7 +24,7 @@ SYMBOLS = (
     "sgl_plan_info", "sgl_plan_profile", "sgl_plan_stage_times", "sgl_destroy", "sgl_status_string",
     "sgl_last_error", "sgl_grad_points", "sgl_cgnr", "sgl_mlp_num_params", "sgl_point_features",
     "sgl_mlp_forward", "sgl_mlp_backward", "sgl_mlp_adam", "sgl_mlp_weights", "sgl_mlp_weight_grad",
-    "sgl_mlp_train_step",
+    "sgl_mlp_train_step", "sgl_batch_create", "sgl_batch_run", "sgl_batch_destroy",
 )
 
 STAGES = ("conv_radial", "conv_polar", "fft_A", "fft_B", "fft_C", "gather", "scatter", "fft_Ch", "fft_Bh",
@@ -75,6 +75,12 @@ def lib():
         L.sgl_grad_points.argtypes, L.sgl_grad_points.restype = [vp, vp, vp, vp, vp], ctypes.c_int
         L.sgl_cgnr.argtypes = [vp, vp, vp, vp, i32, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]
         f32, f64 = ctypes.c_float, ctypes.c_double
+        L.sgl_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), i32, ctypes.POINTER(vp),
+                                       ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), i32, vp]
+        L.sgl_batch_create.restype = ctypes.c_int
+        for name in ("sgl_batch_run", "sgl_batch_destroy"):
+            fn = getattr(L, name)
+            fn.argtypes, fn.restype = [vp], ctypes.c_int
         L.sgl_mlp_num_params.argtypes, L.sgl_mlp_num_params.restype = [], i32
         for name, args in (("sgl_point_features", [vp, vp, vp]), ("sgl_mlp_forward", [vp, vp, vp, vp]),
                            ("sgl_mlp_backward", [vp, vp, vp, vp, vp]),
@@ -392,3 +398,56 @@ class WeightNet:
             im = torch.randn((nbatch, plan.nc), generator=g, device=plan.device, dtype=plan.real_dtype)
             losses.append(self.train_step(plan, feat, torch.complex(re * scale, im * scale), lr))
         return losses
+
+
+class Batch:
+    """The forward and/or adjoint of several plans recorded once as one HIP graph
+    (include/sgl.h, sgl_batch_create) and replayed by ``run()`` with one launch.
+
+    plans: list of Plan; fhats / outs: per-plan coefficient inputs and point
+    outputs of the forward (or None); ys / ghats: point inputs and coefficient
+    outputs of the adjoint (or None).  The tensors are held for the batch's life:
+    every run reads and writes those same buffers.
+    """
+
+    def __init__(self, plans, fhats=None, outs=None, ys=None, ghats=None, nstreams=4, stream=None):
+        import torch
+
+        n = len(plans)
+        self.plans = list(plans)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self._keep = []
+
+        def arr(ts, what, counts):
+            if ts is None:
+                return None
+            if len(ts) != n:
+                raise ValueError(f"{what}: one tensor per plan")
+            for t, p, c in zip(ts, plans, counts):
+                if not t.is_cuda or t.dtype != p.complex_dtype or t.numel() != c(p) or not t.is_contiguous():
+                    raise ValueError(f"{what}: contiguous CUDA {p.complex_dtype} tensors of the plan's size")
+            self._keep.extend(ts)
+            return (ctypes.c_void_p * n)(*[t.data_ptr() for t in ts])
+
+        nc, m = (lambda p: p.nc), (lambda p: p.M)
+        a_fh, a_f = arr(fhats, "fhats", [nc] * n), arr(outs, "outs", [m] * n)
+        a_y, a_g = arr(ys, "ys", [m] * n), arr(ghats, "ghats", [nc] * n)
+        hs = (ctypes.c_void_p * n)(*[p._h.value for p in plans])
+        h = ctypes.c_void_p()
+        _check(lib().sgl_batch_create(ctypes.byref(h), hs, n, a_fh, a_f, a_y, a_g, int(nstreams),
+                                      ctypes.c_void_p(self.stream.cuda_stream)), "sgl_batch_create")
+        self._h = h
+
+    def run(self):
+        _check(lib().sgl_batch_run(self._h), "sgl_batch_run")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().sgl_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -543,6 +543,117 @@ sgl_status sgl_cgnr(sgl_plan_t plan, const void *y_dev, const void *w_dev, void 
   return cgnr_run(p, y_dev, w_dev, fhat_dev, maxiter, tol, info, plan_forward, plan_adjoint);
 }
 
+// ---------------------------------------------------------------- batches
+
+}  // extern "C"
+
+struct sgl_batch_s {
+  hipStream_t stream = nullptr;   // the caller's stream: sgl_batch_run launches here
+  hipStream_t capture = nullptr;  // the stream the graph was captured from
+  std::vector<hipStream_t> side;  // fork branches
+  std::vector<hipEvent_t> events;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+static void batch_free(sgl_batch_s *b) {
+  if (b->exec) hipGraphExecDestroy(b->exec);
+  if (b->graph) hipGraphDestroy(b->graph);
+  for (hipEvent_t e : b->events) hipEventDestroy(e);
+  for (hipStream_t t : b->side) hipStreamDestroy(t);
+  if (b->capture) hipStreamDestroy(b->capture);
+  delete b;
+}
+
+// Captures every plan's forward and/or adjoint on the side streams (plan j on
+// branch j mod nstreams) between a fork and a join on the capture stream.
+static sgl_status batch_capture(sgl_batch_s *b, const sgl_plan_t *plans, int n, const void *const *fhat,
+                                void *const *f, const void *const *y, void *const *ghat) {
+  const int ns = (int)b->side.size();
+  SGL_TRY(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
+  sgl_status st = SGL_OK;
+  hipError_t e = hipEventRecord(b->events[0], b->capture);
+  for (int k = 0; k < ns && e == hipSuccess; ++k) e = hipStreamWaitEvent(b->side[k], b->events[0], 0);
+  for (int j = 0; j < n && e == hipSuccess && st == SGL_OK; ++j) {
+    Plan &p = plans[j]->p;
+    const hipStream_t keep = p.stream;
+    p.stream = b->side[j % ns];
+    if (fhat) st = plan_forward(p, fhat[j], f[j]);
+    if (st == SGL_OK && y) st = plan_adjoint(p, y[j], ghat[j]);
+    p.stream = keep;
+  }
+  for (int k = 0; k < ns && e == hipSuccess; ++k) {
+    e = hipEventRecord(b->events[1 + k], b->side[k]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->capture, b->events[1 + k], 0);
+  }
+  const hipError_t ee = hipStreamEndCapture(b->capture, &b->graph);
+  if (st != SGL_OK) return st;
+  SGL_TRY(e);
+  SGL_TRY(ee);
+  SGL_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  return SGL_OK;
+}
+
+extern "C" {
+
+sgl_status sgl_batch_create(sgl_batch_t *out, const sgl_plan_t *plans, int32_t n, const void *const *fhat_dev,
+                            void *const *f_dev, const void *const *y_dev, void *const *ghat_dev, int32_t nstreams,
+                            void *stream) {
+  if (!out) return SGL_E_INVAL;
+  *out = nullptr;
+  if (!plans || n < 1 || n > 4096 || nstreams < 1 || nstreams > 16) return SGL_E_INVAL;
+  if (!fhat_dev != !f_dev || !y_dev != !ghat_dev || (!fhat_dev && !y_dev)) return SGL_E_INVAL;
+  int dev = -1;
+  for (int j = 0; j < n; ++j) {
+    if (check_plan(plans[j]) != SGL_OK) return SGL_E_INVAL;
+    const Plan &p = plans[j]->p;
+    if (p.prof.on) return SGL_E_INVAL;
+    if (j == 0) dev = p.device;
+    if (p.device != dev) return SGL_E_INVAL;
+    for (int i = 0; i < j; ++i)
+      if (plans[i] == plans[j]) return SGL_E_INVAL;
+    const size_t cb = cbytes(p), nf = sgl_num_coeffs(p.B) * cb, ny = (size_t)p.M * cb;
+    if (fhat_dev && (!fhat_dev[j] || !f_dev[j] || overlaps(fhat_dev[j], nf, f_dev[j], ny))) return SGL_E_INVAL;
+    if (y_dev && (!y_dev[j] || !ghat_dev[j] || overlaps(ghat_dev[j], nf, y_dev[j], ny))) return SGL_E_INVAL;
+  }
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess || cur != dev) return SGL_E_INVAL;
+  sgl_batch_s *b = new (std::nothrow) sgl_batch_s;
+  if (!b) return SGL_E_NOMEM;
+  b->stream = (hipStream_t)stream;
+  hipError_t e = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking);
+  for (int k = 0; k < nstreams && e == hipSuccess; ++k) {
+    hipStream_t t = nullptr;
+    e = hipStreamCreateWithFlags(&t, hipStreamNonBlocking);
+    if (e == hipSuccess) b->side.push_back(t);
+  }
+  for (int k = 0; k <= nstreams && e == hipSuccess; ++k) {
+    hipEvent_t ev = nullptr;
+    e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e == hipSuccess) b->events.push_back(ev);
+  }
+  sgl_status st = from_hip(e);
+  if (st == SGL_OK) st = batch_capture(b, plans, n, fhat_dev, f_dev, y_dev, ghat_dev);
+  if (st != SGL_OK) {
+    batch_free(b);
+    return st;
+  }
+  *out = b;
+  return SGL_OK;
+}
+
+sgl_status sgl_batch_run(sgl_batch_t batch) {
+  if (!batch) return SGL_E_INVAL;
+  return from_hip(hipGraphLaunch(batch->exec, batch->stream));
+}
+
+sgl_status sgl_batch_destroy(sgl_batch_t batch) {
+  if (!batch) return SGL_E_INVAL;
+  hipStreamSynchronize(batch->stream);
+  batch_free(batch);
+  return SGL_OK;
+}
+
 // ---------------------------------------------------------------- learned weights
 
 int32_t sgl_mlp_num_params(void) { return mlp_num_params(); }

@@ -121,6 +121,19 @@ def test_null_arguments():
     assert L.sgl_mlp_weight_grad(None, v, v, v, 1.0, v) == sgl.SGL_E_INVAL
     loss = ctypes.c_double()
     assert L.sgl_mlp_train_step(None, v, v, v, v, v, 1, 1e-3, 1, ctypes.byref(loss)) == sgl.SGL_E_INVAL
+    assert L.sgl_batch_create(None, None, 1, None, None, None, None, 1, None) == sgl.SGL_E_INVAL
+    b = ctypes.c_void_p(123)
+    hs = (ctypes.c_void_p * 2)(16, 32)
+    arr = (ctypes.c_void_p * 2)(64, 4096)
+    # no plans, n = 0, no direction, a direction with one of its two arrays missing, bad branch count
+    assert L.sgl_batch_create(ctypes.byref(b), None, 2, arr, arr, None, None, 1, None) == sgl.SGL_E_INVAL
+    assert b.value is None
+    assert L.sgl_batch_create(ctypes.byref(b), hs, 0, arr, arr, None, None, 1, None) == sgl.SGL_E_INVAL
+    assert L.sgl_batch_create(ctypes.byref(b), hs, 2, None, None, None, None, 1, None) == sgl.SGL_E_INVAL
+    assert L.sgl_batch_create(ctypes.byref(b), hs, 2, arr, None, None, None, 1, None) == sgl.SGL_E_INVAL
+    assert L.sgl_batch_create(ctypes.byref(b), hs, 2, arr, arr, None, None, 0, None) == sgl.SGL_E_INVAL
+    assert L.sgl_batch_create(ctypes.byref(b), hs, 2, arr, arr, None, None, 17, None) == sgl.SGL_E_INVAL
+    assert L.sgl_batch_run(None) == sgl.SGL_E_INVAL and L.sgl_batch_destroy(None) == sgl.SGL_E_INVAL
     assert L.sgl_plan_rho(None, None) == sgl.SGL_E_INVAL
     assert L.sgl_eta_dims(8, None) == sgl.SGL_E_INVAL
 

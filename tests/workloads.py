@@ -122,3 +122,24 @@ def workload(name, seed=0, M=None):
     fhat = coefficients(w["B"], seed + 100, w["decay"])
     y = samples(w["M"], seed + 200)
     return w, pts, fhat, y
+
+
+def _smooth235(v):
+    for p in (2, 3, 5):
+        while v % p == 0:
+            v //= p
+    return v == 1
+
+
+# Bandwidths whose FFT lengths 4B and 8B (sigma = 2) factor into 2, 3 and 5.
+SMOOTH_B = tuple(b for b in range(2, 257) if _smooth235(4 * b) and _smooth235(8 * b))
+
+
+def batch_specs(n=64, seed=0, b_lo=16, b_hi=64, m_lo=1e5, m_hi=2e6):
+    """(B, M) of a batch: B uniform over the supported bandwidths in [b_lo, b_hi],
+    M log-uniform in [m_lo, m_hi]."""
+    rng = np.random.default_rng(seed)
+    bs = [b for b in SMOOTH_B if b_lo <= b <= b_hi]
+    B = rng.choice(bs, n)
+    M = np.exp(rng.uniform(np.log(m_lo), np.log(m_hi), n)).astype(np.int64)
+    return [(int(b), int(m)) for b, m in zip(B, M)]
