@@ -135,10 +135,11 @@ __global__ __launch_bounds__(256) void k_gather_tiled(const cplx<R> *__restrict_
 // (i - o_p)) for 0 <= i - o_p < 2q, zero elsewhere (also past the box).
 typedef _Float16 sgl_half8 __attribute__((ext_vector_type(8)));
 typedef _Float16 sgl_half2 __attribute__((ext_vector_type(2)));
+typedef _Float16 sgl_half4 __attribute__((ext_vector_type(4)));
 typedef float sgl_float4 __attribute__((ext_vector_type(4)));
 typedef float sgl_float2 __attribute__((ext_vector_type(2)));
 
-constexpr int kPlaneK = 24;  // i2 slots per plane row; MFMA K slots 24..31 meet zero weights
+constexpr int kPlaneK = 24;  // i2 slots an MFMA row reads; K slots 24..31 meet zero weights
 constexpr int kLdsMax = 160 * 1024;
 
 template <int Q2>
@@ -148,18 +149,37 @@ struct GatherShape {
   static constexpr int nrow = X * X1p;
   static constexpr int nrb = (nrow + 15) / 16;
   static constexpr int NR = nrb * 16;
+  // Row stride of the planes in halves.  An MFMA row reads kPlaneK slots; the
+  // slots past X belong to the next row (or the pad after the last plane), and
+  // they meet zero weights.  20 halves (40 bytes) keeps the 16 rows of one read
+  // on distinct banks.
+  static constexpr int KS = X <= 20 ? 20 : 24;
   static constexpr int S = ((X1p / 4) % 2 == 0) ? X1p + 4 : X1p;  // w1 floats per point: odd multiple of 4
-  static constexpr size_t plane_bytes = (size_t)4 * NR * kPlaneK * sizeof(_Float16);
+  static constexpr size_t plane_bytes = ((size_t)4 * NR * KS + 8) * sizeof(_Float16);
   static constexpr size_t tab_bytes(int waves) { return (size_t)waves * 32 * S * sizeof(float); }
-  // as many waves as LDS allows (16, 12 or 8); static LDS of the kernel is below 1 KB
-  static constexpr int waves = plane_bytes + tab_bytes(16) + 1024 <= kLdsMax   ? 16
-                               : plane_bytes + tab_bytes(12) + 1024 <= kLdsMax ? 12
-                                                                               : 8;
+  // Two blocks per CU when LDS allows (one block's box staging then overlaps
+  // the other's products), else one block of as many waves as fit.  The
+  // kernel's static LDS is below 1 KB.
+  static constexpr size_t fixed = plane_bytes + 1024;
+  static constexpr int waves2 = fixed + tab_bytes(8) <= kLdsMax / 2   ? 8
+                                : fixed + tab_bytes(6) <= kLdsMax / 2 ? 6
+                                : fixed + tab_bytes(4) <= kLdsMax / 2 ? 4
+                                                                      : 0;
+  static constexpr int waves = waves2                               ? waves2
+                               : fixed + tab_bytes(16) <= kLdsMax   ? 16
+                               : fixed + tab_bytes(12) <= kLdsMax   ? 12
+                                                                    : 8;
   static constexpr int threads = 64 * waves;
-  static constexpr int items = NR * (kPlaneK / 2);  // staged pairs of i2 slots
+  static constexpr int items = NR * (KS / 2);  // staged pairs of i2 slots
   static constexpr int KB = (items + threads - 1) / threads;
   static constexpr size_t lds = plane_bytes + tab_bytes(waves);
 };
+
+// eight halves at p (8-byte aligned)
+__device__ inline sgl_half8 ld_half8(const _Float16 *p) {
+  const sgl_half4 a = *(const sgl_half4 *)p, b = *(const sgl_half4 *)(p + 4);
+  return __builtin_shufflevector(a, b, 0, 1, 2, 3, 4, 5, 6, 7);
+}
 
 template <int Q2>
 __global__ __launch_bounds__(GatherShape<Q2>::threads) void k_gather_mfma(const cplx<float> *__restrict__ grid,
@@ -169,15 +189,15 @@ __global__ __launch_bounds__(GatherShape<Q2>::threads) void k_gather_mfma(const 
                                                                           Geom g, float inv2lam,
                                                                           cplx<float> *__restrict__ f) {
   using Sh = GatherShape<Q2>;
-  constexpr int q = Q2 / 2, X = Sh::X, X1p = Sh::X1p, NR = Sh::NR, S = Sh::S;
+  constexpr int q = Q2 / 2, X = Sh::X, X1p = Sh::X1p, NR = Sh::NR, S = Sh::S, KS = Sh::KS;
   constexpr int NW = Sh::waves, NT = Sh::threads;
-  constexpr int PS = NR * kPlaneK;      // halves per plane
+  constexpr int PS = NR * KS;           // halves per plane
   constexpr int UR = (Q2 >= 10 && Q2 < 16) ? 2 : 1;  // row blocks in flight per wave (as registers allow)
-  static_assert(X <= kPlaneK, "box too long along dimension 2");
+  static_assert(X <= KS && KS <= kPlaneK, "box too long along dimension 2");
   static_assert(Sh::lds + 1024 <= kLdsMax, "LDS budget");
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  _Float16 *plane = (_Float16 *)smem;       // [4][NR][kPlaneK]: re_hi, re_lo, im_hi, im_lo
-  float *wtab = (float *)(plane + 4 * PS);  // [NW][32 points][S]: w1 at [0, X1p)
+  _Float16 *plane = (_Float16 *)smem;           // [4][NR][KS] + 8: re_hi, re_lo, im_hi, im_lo, pad
+  float *wtab = (float *)(plane + 4 * PS + 8);  // [NW][32 points][S]: w1 at [0, X1p)
   __shared__ float red[NW];
   __shared__ int sidx[3][32];
 
@@ -192,6 +212,8 @@ __global__ __launch_bounds__(GatherShape<Q2>::threads) void k_gather_mfma(const 
     const int d = threadIdx.x / 32, i = threadIdx.x % 32;
     const int cd = d == 0 ? c0 : (d == 1 ? c1 : c2);
     sidx[d][i] = i < X ? stored_index(cd * 8 - q + 1 + i, d, g) : -1;
+  } else if (threadIdx.x < 104) {
+    plane[4 * PS + threadIdx.x - 96] = (_Float16)0.0f;  // the pad the last row's read runs into
   }
   __syncthreads();
   // 2. the box (with its zero padding) in registers, pairs of i2 slots per item
@@ -202,7 +224,7 @@ __global__ __launch_bounds__(GatherShape<Q2>::threads) void k_gather_mfma(const 
     const int e = threadIdx.x + u * NT;
     v[u][0] = v[u][1] = cplx<float>{0.0f, 0.0f};
     if (e < Sh::items) {
-      const int r = e / (kPlaneK / 2), kp = e % (kPlaneK / 2);
+      const int r = e / (KS / 2), kp = e % (KS / 2);
       const int i0 = r / X1p, i1 = r % X1p;
       if (i0 < X && i1 < X) {
         const int s0 = sidx[0][i0], s1 = sidx[1][i1];
@@ -233,7 +255,7 @@ __global__ __launch_bounds__(GatherShape<Q2>::threads) void k_gather_mfma(const 
   for (int u = 0; u < Sh::KB; ++u) {
     const int e = threadIdx.x + u * NT;
     if (e < Sh::items) {
-      const int o = (e / (kPlaneK / 2)) * kPlaneK + 2 * (e % (kPlaneK / 2));
+      const int o = (e / (KS / 2)) * KS + 2 * (e % (KS / 2));
       const sgl_float2 re = {v[u][0].re * sc, v[u][1].re * sc}, im = {v[u][0].im * sc, v[u][1].im * sc};
       const sgl_half2 rh = __builtin_convertvector(re, sgl_half2), ih = __builtin_convertvector(im, sgl_half2);
       const sgl_half2 rl = __builtin_convertvector(sgl_float2{re[0] - (float)rh[0], re[1] - (float)rh[1]}, sgl_half2);
@@ -301,17 +323,27 @@ __global__ __launch_bounds__(GatherShape<Q2>::threads) void k_gather_mfma(const 
         bl[gi][j + 1] = ll[1];
       }
     }
+    // rows of box i0 outside every window of the pass have w0 = 0 for all its
+    // points: only the row blocks that meet [min o0, max o0 + Q2) contribute
+    int lo = min(valid[0] ? o0[0] : X, valid[1] ? o0[1] : X);
+    int hi = max(valid[0] ? o0[0] : 0, valid[1] ? o0[1] : 0);
+    for (int o = 1; o < 16; o <<= 1) {
+      lo = min(lo, __shfl_xor(lo, o));
+      hi = max(hi, __shfl_xor(hi, o));
+    }
+    const int rb_lo = __builtin_amdgcn_readfirstlane((lo * X1p) / 16);
+    const int rb_hi = __builtin_amdgcn_readfirstlane(min(Sh::nrb, ((hi + Q2) * X1p + 15) / 16));
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     float ar[2] = {0.0f, 0.0f}, ai[2] = {0.0f, 0.0f};
 #pragma unroll UR
-    for (int rb = 0; rb < Sh::nrb; ++rb) {
-      const _Float16 *ap = plane + (rb * 16 + pl) * kPlaneK + 8 * ha;
-      const sgl_half8 a0 = *(const sgl_half8 *)ap;
-      const sgl_half8 a1 = *(const sgl_half8 *)(ap + PS);
-      const sgl_half8 a2 = *(const sgl_half8 *)(ap + 2 * PS);
-      const sgl_half8 a3 = *(const sgl_half8 *)(ap + 3 * PS);
+    for (int rb = rb_lo; rb < rb_hi; ++rb) {
+      const _Float16 *ap = plane + (rb * 16 + pl) * KS + 8 * ha;
+      const sgl_half8 a0 = ld_half8(ap);
+      const sgl_half8 a1 = ld_half8(ap + PS);
+      const sgl_half8 a2 = ld_half8(ap + 2 * PS);
+      const sgl_half8 a3 = ld_half8(ap + 3 * PS);
       // rows 4h .. 4h+3 of the block: one i0, i1 = i1b .. i1b+3
       const int r4 = rb * 16 + 4 * h;
       const int i0 = r4 / X1p, i1b = r4 - (r4 / X1p) * X1p;
