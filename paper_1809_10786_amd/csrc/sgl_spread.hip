@@ -865,6 +865,7 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_mfma(const cplx<float
   __shared__ __attribute__((aligned(16))) float sfy[kSB][2];  // samples of the batch
   __shared__ float sfr2[kSB];                                 // fractional position along dimension 2
   __shared__ int so2[kSB];                                    // window start along dimension 2 in the box
+  __shared__ int srb[kSB / 32][2];                            // row blocks a K step of 32 points meets
   __shared__ int red[2];                                      // exponents of the loader waves' maxima
 
   const int tidx = chunks[3 * blockIdx.x];
@@ -907,10 +908,10 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_mfma(const cplx<float
     {
       const float fr = role == 0 ? npr.frac[0] : npr.frac[1];
       const int cell = role == 0 ? cell0(npr.cell) : cell1(npr.cell);
+      const int o = cell - ct * 8;  // in [0, 8) for a valid point: it lies in this tile
 #pragma unroll
       for (int i = 0; i < 32; ++i) tab[role][i][pp] = 0.0f;
       if (nvalid) {
-        const int o = cell - ct * 8;  // in [0, 8): the point lies in this tile
 #pragma unroll
         for (int t = 0; t < Q2; ++t) {
           const float dd = fr + (float)(q - 1 - t);
@@ -920,6 +921,17 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_mfma(const cplx<float
       if (role == 0) {
         sfr2[pp] = npr.frac[2];
         so2[pp] = nvalid ? cell2(npr.cell) - c2 * 8 : (1 << 20);
+        // rows i0 * X + i1 with i0 outside [min o0, max o0 + Q2) of a K step's
+        // points have A = 0 there: the step only needs the row blocks between
+        int lo = nvalid ? o : X, hi = nvalid ? o : 0;
+        for (int m = 1; m < 32; m <<= 1) {
+          lo = min(lo, __shfl_xor(lo, m));
+          hi = max(hi, __shfl_xor(hi, m));
+        }
+        if ((pp & 31) == 0) {
+          srb[pp / 32][0] = (lo * X) / 16;
+          srb[pp / 32][1] = min(nrb, ((hi + Q2) * X + 15) / 16);
+        }
       } else {
         const cplx<float> v = nvalid ? ny : cplx<float>{0.0f, 0.0f};
         sfy[pp][0] = v.re;
@@ -980,6 +992,7 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_mfma(const cplx<float
     // 3. products over the batch, K = 32 points per step
     for (int ks = 0; ks < nb; ks += 32) {
       const int p0 = ks + 8 * h;  // this lane's 8 points of the K step
+      const int kr_lo = srb[ks / 32][0], kr_hi = srb[ks / 32][1];
       sgl_half8 brh[2], brl[2], bih[2], bil[2];
 #pragma unroll
       for (int n = 0; n < 2; ++n) {
@@ -992,7 +1005,7 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_mfma(const cplx<float
 #pragma unroll
       for (int r = 0; r < RBW; ++r) {
         const int rb = wave + r * NW;
-        if (rb < nrb) {
+        if (rb < nrb && rb >= kr_lo && rb < kr_hi) {
           // A fragment: row rb * 16 + pl, points p0 .. p0 + 7
           const int row = rb * 16 + pl;
           const int i0 = row / X, i1 = row - (row / X) * X;  // i0 <= X + 15 / X < 32
