@@ -275,11 +275,23 @@ __global__ __launch_bounds__(GatherShape<Q2>::threads) void k_gather_mfma(const 
   const float inv = 1.0f / sc;
   const int npass = (count + 31) / 32;
   float *tb0 = wtab + (size_t)(wave * 32 + pl) * S, *tb1 = tb0 + 16 * S;
+  // the point records of the wave's next pass are loaded while it works on the current one
+  PointRec<float> nxt[2];
+  auto fetch = [&](int ps) {
+#pragma unroll
+    for (int gi = 0; gi < 2; ++gi) {
+      const int idx = ps * 32 + gi * 16 + pl;
+      if (ps < npass && idx < count) nxt[gi] = pts[start + idx];
+    }
+  };
+  fetch(wave);
   for (int ps = wave; ps < npass; ps += NW) {
     sgl_half8 bh[2], bl[2];
     int kk[2], o0[2];
     float d0[2];  // w0 at i0 is gauss(d0 - i0) inside the window
     bool valid[2];
+    const PointRec<float> cur[2] = {nxt[0], nxt[1]};
+    fetch(ps + NW);
 #pragma unroll
     for (int gi = 0; gi < 2; ++gi) {
       const int idx = ps * 32 + gi * 16 + pl;
@@ -289,7 +301,7 @@ __global__ __launch_bounds__(GatherShape<Q2>::threads) void k_gather_mfma(const 
       int o1 = 1 << 20, o2 = 1 << 20;  // outside every box when invalid
       o0[gi] = 1 << 20;
       if (valid[gi]) {
-        const PointRec<float> pr = pts[kk[gi]];
+        const PointRec<float> pr = cur[gi];
         fr0 = pr.frac[0];
         fr1 = pr.frac[1];
         fr2 = pr.frac[2];
