@@ -46,6 +46,8 @@ def parse():
                     help="time 64 heterogeneous transforms (forward + adjoint) eagerly and as one HIP graph")
     ap.add_argument("--conv-split16", action="store_true",
                     help="conversion products on the FP16 matrix cores with hi/lo split operands")
+    ap.add_argument("--sequential", action="store_true",
+                    help="time forward then adjoint on one stream instead of sgl_forward_adjoint")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--check-points", type=int, default=2000)
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -57,7 +59,7 @@ def parse():
 
 
 PROFILE_COMMAND = ("rocprofv3 {mode} -T -f csv -d gpurun_out/prof_{tag} -o {tag} -- python3 bench.py --steps {steps} "
-                   "--warmup 1 --no-cpu-baseline --check-points 0 --copy-calibration 256")
+                   "--warmup 1 --no-cpu-baseline --check-points 0 --copy-calibration 256 --sequential")
 
 
 def spread_flops(q):
@@ -424,23 +426,36 @@ def main():
     for _ in range(a.warmup):
         plan.forward(dfh, out=f)
         plan.adjoint(dy, out=g)
+        if not a.sequential:
+            plan.forward_adjoint(dfh, dy, out=f, out_adj=g)  # the first call sets up the second stream
     torch.cuda.synchronize()
     print("[bench] warmup done", file=sys.stderr, flush=True)
 
-    plan.profile(True)
-    plan.stage_times(reset=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(a.steps):
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / a.steps
+
+    def sequential():
         plan.forward(dfh, out=f)
         plan.adjoint(dy, out=g)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+
+    # the step: forward and adjoint concurrently (sgl_forward_adjoint), no timers
+    ms_seq = timed(sequential)
+    ms_per_step = ms_seq if a.sequential else timed(lambda: plan.forward_adjoint(dfh, dy, out=f, out_adj=g))
+    # per-kernel durations: HIP events on the plan's stream over the same K steps,
+    # run one stage after the other so that every stage is timed on its own
+    plan.profile(True)
+    plan.stage_times(reset=True)
+    timed(sequential)
     stages = plan.stage_times(reset=True)
     plan.profile(False)
-    ms_per_step = elapsed * 1e3 / a.steps
     value = M / (ms_per_step / 1e3)
-    print(f"[bench] {a.steps} steps: {ms_per_step:.3f} ms/step, {value:.4g} points/s", file=sys.stderr, flush=True)
+    print(f"[bench] {a.steps} steps: {ms_per_step:.3f} ms/step, {value:.4g} points/s "
+          f"(forward then adjoint on one stream: {ms_seq:.3f} ms/step)", file=sys.stderr, flush=True)
 
     # per-stage averages and the dominant kernel's roofline position
     avg = {k: v[0] / v[1] for k, v in stages.items()}
@@ -504,6 +519,10 @@ def main():
         "hbm_frac_step": hbm_frac_step,
         "cpu_baseline": cpu,
         "rel_err": acc,
+        "step": "forward + adjoint on one stream" if a.sequential else
+                "sgl_forward_adjoint: forward and adjoint concurrently on two streams",
+        "ms_per_step_one_stream": ms_seq,
+        "stage_timing": "HIP events on the plan's stream over a second pass of the same steps, one stage at a time",
         "stages_ms": {k: round(v, 5) for k, v in avg.items()},
         "plan_ms": plan_ms,
     }

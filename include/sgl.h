@@ -230,6 +230,17 @@ sgl_status sgl_mlp_weight_grad(sgl_plan_t plan, const void *y_dev, const void *g
 sgl_status sgl_mlp_train_step(sgl_plan_t plan, float *params_dev, float *m_dev, float *v_dev, const float *feat_dev,
                               const void *fhat_dev, int32_t nbatch, float lr, int32_t step, double *loss);
 
+/* Forward f = Lambda fhat and adjoint ghat = Lambda^H y in one call, the two
+ * running concurrently: the forward on the plan's stream, the adjoint on a
+ * second stream of the plan with scratch of its own (allocated on the first
+ * call, about the size of the plan's FFT buffers; freed by sgl_destroy).  The
+ * plan's stream waits for both before later work.  Results equal those of
+ * sgl_forward and sgl_adjoint.  With profiling on (sgl_plan_profile) both run
+ * on the plan's stream, one after the other.  No buffer may overlap another
+ * (SGL_E_INVAL). */
+sgl_status sgl_forward_adjoint(sgl_plan_t plan, const void *fhat_dev, void *f_dev, const void *y_dev,
+                               void *ghat_dev);
+
 /* The rho the plan uses (host pointer out). */
 sgl_status sgl_plan_rho(sgl_plan_t plan, double *rho);
 

@@ -24,7 +24,7 @@ SYMBOLS = (
     "sgl_plan_info", "sgl_plan_profile", "sgl_plan_stage_times", "sgl_destroy", "sgl_status_string",
     "sgl_last_error", "sgl_grad_points", "sgl_cgnr", "sgl_mlp_num_params", "sgl_point_features",
     "sgl_mlp_forward", "sgl_mlp_backward", "sgl_mlp_adam", "sgl_mlp_weights", "sgl_mlp_weight_grad",
-    "sgl_mlp_train_step", "sgl_batch_create", "sgl_batch_run", "sgl_batch_destroy",
+    "sgl_mlp_train_step", "sgl_batch_create", "sgl_batch_run", "sgl_batch_destroy", "sgl_forward_adjoint",
 )
 
 STAGES = ("conv_radial", "conv_polar", "fft_A", "fft_B", "fft_C", "gather", "scatter", "fft_Ch", "fft_Bh",
@@ -73,6 +73,7 @@ def lib():
         L.sgl_status_string.argtypes, L.sgl_status_string.restype = [ctypes.c_int], ctypes.c_char_p
         L.sgl_last_error.argtypes, L.sgl_last_error.restype = [], ctypes.c_char_p
         L.sgl_grad_points.argtypes, L.sgl_grad_points.restype = [vp, vp, vp, vp, vp], ctypes.c_int
+        L.sgl_forward_adjoint.argtypes, L.sgl_forward_adjoint.restype = [vp, vp, vp, vp, vp], ctypes.c_int
         L.sgl_cgnr.argtypes = [vp, vp, vp, vp, i32, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]
         f32, f64 = ctypes.c_float, ctypes.c_double
         L.sgl_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), i32, ctypes.POINTER(vp),
@@ -209,6 +210,17 @@ class Plan:
         y = self._out(self.nc, out)
         self._call("sgl_adjoint", x, y)
         return y
+
+    def forward_adjoint(self, fhat, y, out=None, out_adj=None):
+        """(Lambda fhat, Lambda^H y), the two computed concurrently on two streams."""
+        fh = self._in(fhat, self.nc, "fhat")
+        yy = self._in(y, self.M, "y")
+        f = self._out(self.M, out)
+        g = self._out(self.nc, out_adj)
+        _check(lib().sgl_forward_adjoint(self._h, ctypes.c_void_p(fh.data_ptr()), ctypes.c_void_p(f.data_ptr()),
+                                         ctypes.c_void_p(yy.data_ptr()), ctypes.c_void_p(g.data_ptr())),
+               "sgl_forward_adjoint")
+        return f, g
 
     def conv_forward(self, fhat, out=None):
         x = self._in(fhat, self.nc, "fhat")

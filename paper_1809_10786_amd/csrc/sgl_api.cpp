@@ -16,6 +16,11 @@ using namespace sgl;
 
 struct sgl_plan_s {
   Plan p;
+  // sgl_forward_adjoint: the adjoint runs on a second stream with scratch of
+  // its own (a copy of p sharing every read-only array), set up on first use
+  bool paired = false;
+  sgl::Plan adj;
+  hipEvent_t fork = nullptr, join = nullptr;
 };
 
 namespace {
@@ -76,6 +81,30 @@ hipError_t dev_alloc(Plan &p, T **ptr, size_t bytes) {
     p.bytes += bytes;
   }
   return e;
+}
+
+// The scratch one transform direction writes: beta, compact zeta, eta and the
+// two FFT buffers (double values on the adjoint side in both precisions).
+hipError_t alloc_scratch(Plan &p) {
+  const int B = p.B;
+  const size_t nbeta = (size_t)(2 * B - 1) * B * B;  // sum_m (B - |m|) (2B - 1) = B^2 (2B - 1)
+  const size_t neta = (size_t)p.n[0] * p.n[1] * p.n[2];
+  const size_t nT1 = (size_t)p.n[0] * p.n[1] * p.N[2];
+  const size_t nT2 = (size_t)p.n[0] * p.E[1] * p.N[2];
+  const size_t nG = (size_t)p.E[0] * p.E[1] * p.E[2];
+  hipError_t e = dev_alloc(p, &p.beta, nbeta * 16);
+  if (e == hipSuccess) e = dev_alloc(p, &p.zeta, (size_t)(2 * B - 1) * B * (2 * B - 1) * 16);
+  if (e == hipSuccess) e = dev_alloc(p, &p.eta, neta * 16);
+  if (e == hipSuccess) e = dev_alloc(p, &p.bufX, std::max(nT1, nG) * 16);
+  if (e == hipSuccess) e = dev_alloc(p, &p.bufY, nT2 * 16);
+  return e;
+}
+
+void free_scratch(Plan &p) {
+  void *bufs[] = {p.beta, p.zeta, p.eta, p.bufX, p.bufY};
+  for (void *b : bufs)
+    if (b) hipFree(b);
+  p.beta = p.zeta = p.eta = p.bufX = p.bufY = nullptr;
 }
 
 template <class R>
@@ -278,19 +307,7 @@ sgl_status make_plan(Plan &p, const void *points) {
   const sgl_status st = p.prec == SGL_F64 ? build_tables<double>(p) : build_tables<float>(p);
   if (st != SGL_OK) return st;
   // 6. workspace
-  const size_t cb = cbytes(p);
-  const int B = p.B;
-  const size_t nbeta = (size_t)(2 * B - 1) * B * B;  // sum_m (B - |m|) (2B - 1) = B^2 (2B - 1)
-  const size_t neta = (size_t)p.n[0] * p.n[1] * p.n[2];
-  const size_t nT1 = (size_t)p.n[0] * p.n[1] * p.N[2];
-  const size_t nT2 = (size_t)p.n[0] * p.E[1] * p.N[2];
-  const size_t nG = (size_t)p.E[0] * p.E[1] * p.E[2];
-  SGL_TRY(dev_alloc(p, &p.beta, nbeta * 16));
-  SGL_TRY(dev_alloc(p, &p.zeta, (size_t)(2 * B - 1) * B * (2 * B - 1) * 16));  // compact zeta
-  // eta and the FFT scratch hold double values on the adjoint side in both precisions
-  SGL_TRY(dev_alloc(p, &p.eta, neta * 16));
-  SGL_TRY(dev_alloc(p, &p.bufX, std::max(nT1, nG) * 16));
-  SGL_TRY(dev_alloc(p, &p.bufY, nT2 * 16));
+  SGL_TRY(alloc_scratch(p));
   SGL_TRY(hipStreamSynchronize(p.stream));
   return SGL_OK;
 }
@@ -787,6 +804,57 @@ sgl_status sgl_adjoint(sgl_plan_t plan, const void *f_dev, void *fhat_dev) {
   return plan_adjoint(p, f_dev, fhat_dev);
 }
 
+// Second scratch set and stream for sgl_forward_adjoint.
+static sgl_status pair_setup(sgl_plan_s *h) {
+  if (h->paired) return SGL_OK;
+  Plan a = h->p;  // shares every read-only array of the plan
+  a.prof = Profiler();
+  a.beta = a.zeta = a.eta = a.bufX = a.bufY = nullptr;
+  a.stream = nullptr;
+  hipError_t e = alloc_scratch(a);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&a.stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&h->fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&h->join, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    free_scratch(a);
+    if (a.stream) hipStreamDestroy(a.stream);
+    if (h->fork) hipEventDestroy(h->fork);
+    if (h->join) hipEventDestroy(h->join);
+    h->fork = h->join = nullptr;
+    return from_hip(e);
+  }
+  h->adj = a;
+  h->paired = true;
+  return SGL_OK;
+}
+
+sgl_status sgl_forward_adjoint(sgl_plan_t plan, const void *fhat_dev, void *f_dev, const void *y_dev,
+                               void *ghat_dev) {
+  if (check_plan(plan) != SGL_OK || !fhat_dev || !f_dev || !y_dev || !ghat_dev) return SGL_E_INVAL;
+  Plan &p = plan->p;
+  const size_t cb = cbytes(p), nf = sgl_num_coeffs(p.B) * cb, ny = (size_t)p.M * cb;
+  if (overlaps(fhat_dev, nf, f_dev, ny) || overlaps(ghat_dev, nf, y_dev, ny) || overlaps(f_dev, ny, y_dev, ny) ||
+      overlaps(f_dev, ny, ghat_dev, nf) || overlaps(fhat_dev, nf, ghat_dev, nf))
+    return SGL_E_INVAL;
+  if (p.prof.on) {  // one stream, so that every stage is timed on its own
+    const sgl_status st = plan_forward(p, fhat_dev, f_dev);
+    return st != SGL_OK ? st : plan_adjoint(p, y_dev, ghat_dev);
+  }
+  sgl_status st = pair_setup(plan);
+  if (st != SGL_OK) return st;
+  Plan &a = plan->adj;
+  SGL_TRY(hipEventRecord(plan->fork, p.stream));
+  SGL_TRY(hipStreamWaitEvent(a.stream, plan->fork, 0));
+  st = plan_forward(p, fhat_dev, f_dev);
+  const sgl_status sa = plan_adjoint(a, y_dev, ghat_dev);
+  // the caller's stream waits for the adjoint, whatever happened on either side
+  const hipError_t e1 = hipEventRecord(plan->join, a.stream);
+  const hipError_t e2 = e1 == hipSuccess ? hipStreamWaitEvent(p.stream, plan->join, 0) : e1;
+  if (st != SGL_OK) return st;
+  if (sa != SGL_OK) return sa;
+  return from_hip(e2);
+}
+
 sgl_status sgl_plan_rho(sgl_plan_t plan, double *rho) {
   if (check_plan(plan) != SGL_OK || !rho) return SGL_E_INVAL;
   *rho = plan->p.rho;
@@ -847,6 +915,13 @@ sgl_status sgl_destroy(sgl_plan_t plan) {
   if (!plan) return SGL_E_INVAL;
   prof_release(plan->p);
   hipStreamSynchronize(plan->p.stream);
+  if (plan->paired) {
+    hipStreamSynchronize(plan->adj.stream);
+    free_scratch(plan->adj);
+    hipStreamDestroy(plan->adj.stream);
+    hipEventDestroy(plan->fork);
+    hipEventDestroy(plan->join);
+  }
   free_plan(plan->p);
   delete plan;
   return SGL_OK;

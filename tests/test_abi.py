@@ -134,6 +134,7 @@ def test_null_arguments():
     assert L.sgl_batch_create(ctypes.byref(b), hs, 2, arr, arr, None, None, 0, None) == sgl.SGL_E_INVAL
     assert L.sgl_batch_create(ctypes.byref(b), hs, 2, arr, arr, None, None, 17, None) == sgl.SGL_E_INVAL
     assert L.sgl_batch_run(None) == sgl.SGL_E_INVAL and L.sgl_batch_destroy(None) == sgl.SGL_E_INVAL
+    assert L.sgl_forward_adjoint(None, v, v, v, v) == sgl.SGL_E_INVAL
     assert L.sgl_plan_rho(None, None) == sgl.SGL_E_INVAL
     assert L.sgl_eta_dims(8, None) == sgl.SGL_E_INVAL
 

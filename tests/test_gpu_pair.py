@@ -1,0 +1,47 @@
+"""sgl_forward_adjoint: the forward and the adjoint of one plan running
+concurrently on two streams give exactly (bit for bit) what sgl_forward and
+sgl_adjoint give, over repeated calls with new inputs, with profiling on (one
+stream) and on a plan whose stream is not the default one; overlapping
+buffers are rejected."""
+import numpy as np
+import pytest
+
+from tests import workloads as wl
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.mark.parametrize("B,M,prec,own_stream", [(32, 100_000, "f32", False), (8, 5_001, "f64", True),
+                                                  (64, 300_000, "f32", True)])
+def test_forward_adjoint_equals_separate_calls(B, M, prec, own_stream):
+    import paper_1809_10786_amd as sgl
+
+    say(f"forward_adjoint B={B} M={M} {prec} own_stream={own_stream}")
+    rt, ct = (torch.float64, torch.complex128) if prec == "f64" else (torch.float32, torch.complex64)
+    P = torch.from_numpy(wl.mixed_points(M, 500)).to("cuda", rt)
+    stream = torch.cuda.Stream() if own_stream else None
+    plan = sgl.Plan(P, B, precision=prec, stream=stream)
+    with torch.cuda.stream(plan.stream):
+        for rep in range(3):
+            fh = torch.from_numpy(wl.coefficients(B, 510 + rep)).to("cuda", ct)
+            y = torch.from_numpy(wl.samples(M, 520 + rep)).to("cuda", ct)
+            f2, g2 = plan.forward_adjoint(fh, y)
+            f1 = plan.forward(fh)
+            g1 = plan.adjoint(y)
+            torch.cuda.synchronize()
+            assert torch.equal(f1, f2) and torch.equal(g1, g2), rep
+        plan.profile(True)
+        f3, g3 = plan.forward_adjoint(fh, y)
+        torch.cuda.synchronize()
+        st = plan.stage_times()
+        plan.profile(False)
+        assert torch.equal(f1, f3) and torch.equal(g1, g3)
+        assert "gather" in st or "ndft" in st
+        with pytest.raises(sgl.SglError):
+            plan.forward_adjoint(fh, y, out=y)  # f would overwrite y while the adjoint reads it
+    plan.close()
