@@ -66,7 +66,7 @@ int lines_per_group(int L, size_t elem) {
 
 void free_plan(Plan &p) {
   void *bufs[] = {p.pts, p.perm, p.tile_start, p.chunks, p.krad, p.kpol, p.deconv, p.twiddle, p.beta,
-                  p.zeta, p.eta, p.bufX, p.bufY, p.ptsxyz, p.tile_chunk, p.staging};
+                  p.zeta, p.eta, p.bufX, p.bufY, p.bufZ, p.ptsxyz, p.tile_chunk, p.staging};
   for (void *b : bufs)
     if (b) hipFree(b);
   free_conv_tables(p);
@@ -89,22 +89,23 @@ hipError_t alloc_scratch(Plan &p) {
   const int B = p.B;
   const size_t nbeta = (size_t)(2 * B - 1) * B * B;  // sum_m (B - |m|) (2B - 1) = B^2 (2B - 1)
   const size_t neta = (size_t)p.n[0] * p.n[1] * p.n[2];
-  const size_t nT1 = (size_t)p.n[0] * p.n[1] * p.N[2];
-  const size_t nT2 = (size_t)p.n[0] * p.E[1] * p.N[2];
+  const size_t n01 = (size_t)p.n[0] * p.E[1] * p.n[2];  // after the dimension-1 pass
+  const size_t nEE = (size_t)p.E[0] * p.E[1] * p.n[2];  // after dimensions 0 and 1 (or 2, adjoint)
   const size_t nG = (size_t)p.E[0] * p.E[1] * p.E[2];
   hipError_t e = dev_alloc(p, &p.beta, nbeta * 16);
   if (e == hipSuccess) e = dev_alloc(p, &p.zeta, (size_t)(2 * B - 1) * B * (2 * B - 1) * 16);
   if (e == hipSuccess) e = dev_alloc(p, &p.eta, neta * 16);
-  if (e == hipSuccess) e = dev_alloc(p, &p.bufX, std::max(nT1, nG) * 16);
-  if (e == hipSuccess) e = dev_alloc(p, &p.bufY, nT2 * 16);
+  if (e == hipSuccess) e = dev_alloc(p, &p.bufX, nG * 16);
+  if (e == hipSuccess) e = dev_alloc(p, &p.bufY, std::max(n01, nEE) * 16);
+  if (e == hipSuccess) e = dev_alloc(p, &p.bufZ, std::max(n01, nEE) * 16);
   return e;
 }
 
 void free_scratch(Plan &p) {
-  void *bufs[] = {p.beta, p.zeta, p.eta, p.bufX, p.bufY};
+  void *bufs[] = {p.beta, p.zeta, p.eta, p.bufX, p.bufY, p.bufZ};
   for (void *b : bufs)
     if (b) hipFree(b);
-  p.beta = p.zeta = p.eta = p.bufX = p.bufY = nullptr;
+  p.beta = p.zeta = p.eta = p.bufX = p.bufY = p.bufZ = nullptr;
 }
 
 template <class R>
@@ -201,8 +202,12 @@ sgl_status setup_geometry(Plan &p) {
     rows *= std::min<int64_t>(p.T[j], span / p.L[j] + 2 + (p.pruned[j] ? 0 : 2));
   }
   if (rows > 512) return SGL_E_UNSUPPORTED;
-  // FFT passes: [outer][axis][inner] views; every pass computes in FP64
+  // FFT passes: [outer][axis][inner] views; every pass computes in FP64.  The
+  // forward runs dimension 1 (n1 -> E1 rows), 0 (n0 -> E0) and last 2, the one
+  // that doubles (n2 -> N2), so both intermediates stay near the size of eta;
+  // the adjoint runs the mirror order (2, 0, 1).
   auto pass = [&](FftPass &fp, int j, int outer, int inner, int nin, int in_off, int nout, int out_off, int sign) {
+    fp.axis = j;
     radices_of(p.N[j], fp);
     fp.outer = outer;
     fp.inner = inner;
@@ -214,12 +219,13 @@ sgl_status setup_geometry(Plan &p) {
     fp.W = lines_per_group(p.N[j], 16);
   };
   const int n0 = p.n[0], n1 = p.n[1], n2 = p.n[2];
-  pass(p.passA, 2, n0 * n1, 1, n2, -n2 / 2, p.N[2], 0, +1);
-  pass(p.passB, 1, n0, p.N[2], n1, -n1 / 2, p.E[1], p.lo[1], +1);
-  pass(p.passC, 0, 1, p.E[1] * p.N[2], n0, -n0 / 2, p.E[0], p.lo[0], +1);
-  pass(p.passCh, 0, 1, p.E[1] * p.N[2], p.E[0], p.lo[0], n0, -n0 / 2, -1);
-  pass(p.passBh, 1, n0, p.N[2], p.E[1], p.lo[1], n1, -n1 / 2, -1);
-  pass(p.passAh, 2, n0 * n1, 1, p.N[2], 0, n2, -n2 / 2, -1);
+  const int E0 = p.E[0], E1 = p.E[1];
+  pass(p.passA, 1, n0, n2, n1, -n1 / 2, E1, p.lo[1], +1);             // eta [n0][n1][n2] -> [n0][E1][n2]
+  pass(p.passB, 0, 1, E1 * n2, n0, -n0 / 2, E0, p.lo[0], +1);         // -> [E0][E1][n2]
+  pass(p.passC, 2, E0 * E1, 1, n2, -n2 / 2, p.N[2], 0, +1);           // -> grid [E0][E1][N2]
+  pass(p.passCh, 2, E0 * E1, 1, p.N[2], 0, n2, -n2 / 2, -1);          // grid -> [E0][E1][n2]
+  pass(p.passBh, 0, 1, E1 * n2, E0, p.lo[0], n0, -n0 / 2, -1);        // -> [n0][E1][n2]
+  pass(p.passAh, 1, n0, n2, E1, p.lo[1], n1, -n1 / 2, -1);            // -> eta [n0][n1][n2]
   return SGL_OK;
 }
 
@@ -381,9 +387,9 @@ sgl_status nfft_fwd(Plan &p, const void *eta, int eta_f64, void *f) {
     return SGL_OK;
   }
   const int grid_f64 = p.prec == SGL_F64;
-  SGL_STAGE(SGL_STAGE_FFT_A, launch_fft_pass(p, p.passA, eta, p.bufX, 2, 1, eta_f64, 1));
-  SGL_STAGE(SGL_STAGE_FFT_B, launch_fft_pass(p, p.passB, p.bufX, p.bufY, 1, 0, 1, 1));
-  SGL_STAGE(SGL_STAGE_FFT_C, launch_fft_pass(p, p.passC, p.bufY, p.bufX, 0, 0, 1, grid_f64));
+  SGL_STAGE(SGL_STAGE_FFT_A, launch_fft_pass(p, p.passA, eta, p.bufY, 1, 1, eta_f64, 1));
+  SGL_STAGE(SGL_STAGE_FFT_B, launch_fft_pass(p, p.passB, p.bufY, p.bufZ, 0, 0, 1, 1));
+  SGL_STAGE(SGL_STAGE_FFT_C, launch_fft_pass(p, p.passC, p.bufZ, p.bufX, 2, 0, 1, grid_f64));
   SGL_STAGE(SGL_STAGE_GATHER, launch_gather(p, p.bufX, f));
   return SGL_OK;
 }
@@ -399,9 +405,9 @@ sgl_status nfft_adj(Plan &p, const void *f, void *eta, int eta_f64) {
   if (p.gather_mode == 0) SGL_STAGE(SGL_STAGE_FOLD, launch_fold(p, p.bufX));
   // the folded grid is double; the direct scatter writes the plan's precision
   const int grid_f64 = (p.gather_mode == 0 || p.prec == SGL_F64) ? 1 : 0;
-  SGL_STAGE(SGL_STAGE_FFT_CH, launch_fft_pass(p, p.passCh, p.bufX, p.bufY, 0, 0, grid_f64, 1));
-  SGL_STAGE(SGL_STAGE_FFT_BH, launch_fft_pass(p, p.passBh, p.bufY, p.bufX, 1, 0, 1, 1));
-  SGL_STAGE(SGL_STAGE_FFT_AH, launch_fft_pass(p, p.passAh, p.bufX, eta, 2, 2, 1, eta_f64));
+  SGL_STAGE(SGL_STAGE_FFT_CH, launch_fft_pass(p, p.passCh, p.bufX, p.bufY, 2, 0, grid_f64, 1));
+  SGL_STAGE(SGL_STAGE_FFT_BH, launch_fft_pass(p, p.passBh, p.bufY, p.bufZ, 0, 0, 1, 1));
+  SGL_STAGE(SGL_STAGE_FFT_AH, launch_fft_pass(p, p.passAh, p.bufZ, eta, 1, 2, 1, eta_f64));
   return SGL_OK;
 }
 
@@ -526,9 +532,9 @@ sgl_status sgl_grad_points(sgl_plan_t plan, const void *fhat_dev, const void *po
   // the forward grid (conversion and FFT as in sgl_forward), then the gradient gather
   const sgl_status st = conv_fwd(p, fhat_dev, p.eta, 1);
   if (st != SGL_OK) return st;
-  SGL_STAGE(SGL_STAGE_FFT_A, launch_fft_pass(p, p.passA, p.eta, p.bufX, 2, 1, 1, 1));
-  SGL_STAGE(SGL_STAGE_FFT_B, launch_fft_pass(p, p.passB, p.bufX, p.bufY, 1, 0, 1, 1));
-  SGL_STAGE(SGL_STAGE_FFT_C, launch_fft_pass(p, p.passC, p.bufY, p.bufX, 0, 0, 1, p.prec == SGL_F64));
+  SGL_STAGE(SGL_STAGE_FFT_A, launch_fft_pass(p, p.passA, p.eta, p.bufY, 1, 1, 1, 1));
+  SGL_STAGE(SGL_STAGE_FFT_B, launch_fft_pass(p, p.passB, p.bufY, p.bufZ, 0, 0, 1, 1));
+  SGL_STAGE(SGL_STAGE_FFT_C, launch_fft_pass(p, p.passC, p.bufZ, p.bufX, 2, 0, 1, p.prec == SGL_F64));
   SGL_STAGE(SGL_STAGE_GATHER, launch_grad_points(p, p.bufX, points_dev, g_dev, grad_dev));
   return SGL_OK;
 }
@@ -809,7 +815,7 @@ static sgl_status pair_setup(sgl_plan_s *h) {
   if (h->paired) return SGL_OK;
   Plan a = h->p;  // shares every read-only array of the plan
   a.prof = Profiler();
-  a.beta = a.zeta = a.eta = a.bufX = a.bufY = nullptr;
+  a.beta = a.zeta = a.eta = a.bufX = a.bufY = a.bufZ = nullptr;
   a.stream = nullptr;
   hipError_t e = alloc_scratch(a);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&a.stream, hipStreamNonBlocking);

@@ -133,15 +133,30 @@ __device__ inline int wrap(int i, int L) {
   return i < 0 ? i + L : i;
 }
 
-// dcmode: 0 none; 1 multiply input row i of line o by dc0[o / n1] dc1[o % n1]
-// dc2[i]; 2 the same on output rows (pass A of the forward / adjoint).
+// Deconvolution factor dc0[k0] dc1[k1] dc2[k2] of an element of the reduced
+// grid [n0][n1][n2], split for a pass along `axis` ([outer][axis][inner] view
+// of that grid) into the factor of the line (outer index o, inner index ic)
+// and the factor of the element's index i along the axis.
+__device__ inline double dc_line(const double *dc, int axis, int o, int ic, int n0, int n1, int n2) {
+  if (axis == 2) return dc[o / n1] * dc[n0 + o % n1];
+  if (axis == 1) return dc[o] * dc[n0 + n1 + ic];
+  return dc[n0 + ic / n2] * dc[n0 + n1 + ic % n2];
+}
+
+__device__ inline double dc_elem(const double *dc, int axis, int i, int n0, int n1) {
+  return dc[axis == 0 ? i : (axis == 1 ? n0 + i : n0 + n1 + i)];
+}
+
+// dcmode: 0 none; 1 multiply the input rows by the deconvolution factor (the
+// first pass of the forward reads the reduced grid); 2 the same on the output
+// rows (the last pass of the adjoint writes it).
 // Ri: element type read, Ro: element type written; the transform itself runs
 // in FP64 (the grid's values span many orders of magnitude towards r = rho and
 // an FP32 transform leaves errors of the size of the largest ones everywhere).
 template <class Ri, class Ro>
 __global__ __launch_bounds__(256) void k_fft(const cplx<Ri> *__restrict__ in, cplx<Ro> *__restrict__ out, FftPass fp,
                                              const cplx<double> *__restrict__ tw64, const double *__restrict__ dc,
-                                             int dcmode, int n0, int n1) {
+                                             int dcmode, int n0, int n1, int n2) {
   using R = double;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int L = fp.L, W = fp.W;
@@ -178,7 +193,7 @@ __global__ __launch_bounds__(256) void k_fft(const cplx<Ri> *__restrict__ in, cp
     if (o >= fp.outer || ic >= fp.inner) continue;
     const cplx<Ri> vi = in[((size_t)o * fp.nin + i) * fp.inner + ic];
     cplx<R> v = {(R)vi.re, (R)vi.im};
-    if (dcmode == 1) v = cscale(v, (R)(dc[o / n1] * dc[n0 + o % n1] * dc[n0 + n1 + i]));
+    if (dcmode == 1) v = cscale(v, (R)(dc_line(dc, fp.axis, o, ic, n0, n1, n2) * dc_elem(dc, fp.axis, i, n0, n1)));
     buf0[wrap(fp.in_off + i, L) * W + w] = v;
   }
   __syncthreads();
@@ -214,7 +229,7 @@ __global__ __launch_bounds__(256) void k_fft(const cplx<Ri> *__restrict__ in, cp
     const int ic = fp.inner > 1 ? ic_base + w : 0;
     if (o >= fp.outer || ic >= fp.inner) continue;
     cplx<R> v = src[wrap(fp.out_off + i, L) * W + w];
-    if (dcmode == 2) v = cscale(v, (R)(dc[o / n1] * dc[n0 + o % n1] * dc[n0 + n1 + i]));
+    if (dcmode == 2) v = cscale(v, (R)(dc_line(dc, fp.axis, o, ic, n0, n1, n2) * dc_elem(dc, fp.axis, i, n0, n1)));
     out[((size_t)o * fp.nout + i) * fp.inner + ic] = cplx<Ro>{(Ro)v.re, (Ro)v.im};
   }
 }
@@ -302,7 +317,7 @@ __device__ inline void p2_stages8(cplx<R> *buf, const cplx<R> *tw, int sign) {
 template <class Ri, class Ro, int LOG2L, bool STRIDED>
 __global__ __launch_bounds__((p2_threads<double, LOG2L, STRIDED>())) void k_fft_p2(
     const cplx<Ri> *__restrict__ in, cplx<Ro> *__restrict__ out, FftPass fp, const cplx<double> *__restrict__ tw64,
-    const double *__restrict__ dc, int dcmode, int n0, int n1) {
+    const double *__restrict__ dc, int dcmode, int n0, int n1, int n2) {
   using R = double;  // the transform runs in FP64 (see k_fft)
   constexpr int L = 1 << LOG2L;
   constexpr int W = p2_lines<R, LOG2L, STRIDED>();
@@ -312,7 +327,7 @@ __global__ __launch_bounds__((p2_threads<double, LOG2L, STRIDED>())) void k_fft_
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   cplx<R> *buf = (cplx<R> *)smem;
   cplx<R> *tw = buf + (size_t)L * SW;  // twiddles e^{2 pi i t / L} in the transform's precision
-  __shared__ double linefac[W];        // deconvolution factor of dimensions 0 and 1 per line
+  __shared__ double linefac[W];        // deconvolution factor of the line (dimensions other than the axis)
   for (int t = threadIdx.x; t < L; t += NT) tw[t] = cplx<R>{(R)tw64[t].re, (R)tw64[t].im};
 
   int o_base, ic_base;
@@ -326,7 +341,8 @@ __global__ __launch_bounds__((p2_threads<double, LOG2L, STRIDED>())) void k_fft_
   }
   if (dcmode != 0 && threadIdx.x < W) {
     const int o = STRIDED ? o_base : o_base + (int)threadIdx.x;
-    linefac[threadIdx.x] = o < fp.outer ? dc[o / n1] * dc[n0 + o % n1] : 0.0;
+    const int ic = STRIDED ? ic_base + (int)threadIdx.x : 0;
+    linefac[threadIdx.x] = o < fp.outer && ic < fp.inner ? dc_line(dc, fp.axis, o, ic, n0, n1, n2) : 0.0;
   }
   for (int e = threadIdx.x; e < L * SW; e += NT) buf[e] = cplx<R>{0, 0};
   __syncthreads();
@@ -345,7 +361,7 @@ __global__ __launch_bounds__((p2_threads<double, LOG2L, STRIDED>())) void k_fft_
     if (o >= fp.outer || ic >= fp.inner) continue;
     const cplx<Ri> vi = in[((size_t)o * fp.nin + i) * fp.inner + ic];
     cplx<R> v = {(R)vi.re, (R)vi.im};
-    if (dcmode == 1) v = cscale(v, (R)(linefac[w] * dc[n0 + n1 + i]));
+    if (dcmode == 1) v = cscale(v, (R)(linefac[w] * dc_elem(dc, fp.axis, i, n0, n1)));
     buf[((fp.in_off + i) & (L - 1)) * SW + w] = v;
   }
   __syncthreads();
@@ -366,7 +382,7 @@ __global__ __launch_bounds__((p2_threads<double, LOG2L, STRIDED>())) void k_fft_
     const int ic = STRIDED ? ic_base + w : 0;
     if (o >= fp.outer || ic >= fp.inner) continue;
     cplx<R> v = buf[((fp.out_off + i) & (L - 1)) * SW + w];
-    if (dcmode == 2) v = cscale(v, (R)(linefac[w] * dc[n0 + n1 + i]));
+    if (dcmode == 2) v = cscale(v, (R)(linefac[w] * dc_elem(dc, fp.axis, i, n0, n1)));
     out[((size_t)o * fp.nout + i) * fp.inner + ic] = cplx<Ro>{(Ro)v.re, (Ro)v.im};
   }
 }
@@ -380,7 +396,7 @@ hipError_t fft_p2s(const Plan &p, const FftPass &fp, const void *in, void *out, 
   const size_t lds = ((size_t)(1 << LOG2L) * SW + (1 << LOG2L)) * sizeof(cplx<double>);
   k_fft_p2<Ri, Ro, LOG2L, STRIDED><<<groups, NT, lds, p.stream>>>(
       (const cplx<Ri> *)in, (cplx<Ro> *)out, fp, (const cplx<double> *)p.twiddle + p.tw_off[tw_index],
-      (const double *)p.deconv, dcmode, p.n[0], p.n[1]);
+      (const double *)p.deconv, dcmode, p.n[0], p.n[1], p.n[2]);
   return hipGetLastError();
 }
 
@@ -419,7 +435,7 @@ hipError_t fft_typed(const Plan &p, const FftPass &fp, const void *in, void *out
   const size_t lds = (2 * (size_t)fp.L * fp.W + fp.L) * sizeof(cplx<double>);
   k_fft<Ri, Ro><<<groups, 256, lds, p.stream>>>((const cplx<Ri> *)in, (cplx<Ro> *)out, fp,
                                                 (const cplx<double> *)p.twiddle + p.tw_off[tw_index],
-                                                (const double *)p.deconv, dcmode, p.n[0], p.n[1]);
+                                                (const double *)p.deconv, dcmode, p.n[0], p.n[1], p.n[2]);
   return hipGetLastError();
 }
 

@@ -61,6 +61,7 @@ constexpr int kMaxStages = 12;
 // o < nout take FFT index (out_off + o) mod L.  `scale_*` are optional real
 // factors (deconvolution) applied along axis on input or output.
 struct FftPass {
+  int axis;          // grid dimension the lines run along
   int L;             // transform length
   int nstages;
   int radix[kMaxStages];
@@ -136,7 +137,8 @@ struct Plan {
   void *zeta = nullptr;   // polar output in compact form, complex double
   void *eta = nullptr;    // dense eta on the reduced grid (complex double in both precisions)
   void *bufX = nullptr;   // FFT scratch T1 and the stored grid G (aliased)
-  void *bufY = nullptr;   // FFT scratch T2
+  void *bufY = nullptr;   // FFT scratch (first pass output)
+  void *bufZ = nullptr;   // FFT scratch (second pass output)
   void *ptsxyz = nullptr; // for the exact NDFT: transformed points t (double, 3 x M)
   size_t bytes = 0;
   FftPass passA, passB, passC;      // forward passes (evaluation sign)
