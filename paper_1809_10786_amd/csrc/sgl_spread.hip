@@ -155,22 +155,21 @@ struct GatherShape {
   // on distinct banks.
   static constexpr int KS = X <= 20 ? 20 : 24;
   static constexpr int S = ((X1p / 4) % 2 == 0) ? X1p + 4 : X1p;  // w1 floats per point: odd multiple of 4
-  static constexpr size_t plane_bytes = ((size_t)4 * NR * KS + 8) * sizeof(_Float16);
+  // Planes hold nrow rows each.  The last row block reads NR - nrow rows past a
+  // plane's end, which lie in the next plane (or in the zeroed tail after the
+  // last one); they meet w0 = 0 (i0 past the box), so any finite value serves.
+  static constexpr int PS = nrow * KS;  // halves per plane
+  static constexpr int tail = (NR - nrow) * KS + 8;
+  static constexpr size_t plane_bytes = ((size_t)4 * PS + tail) * sizeof(_Float16);
   static constexpr size_t tab_bytes(int waves) { return (size_t)waves * 32 * S * sizeof(float); }
+  static constexpr size_t static_bytes(int waves) { return 4 * waves + 3 * 32 * 4; }  // red, sidx
+  static constexpr size_t need(int waves) { return plane_bytes + tab_bytes(waves) + static_bytes(waves); }
   // Two blocks per CU when LDS allows (one block's box staging then overlaps
-  // the other's products), else one block of as many waves as fit.  The
-  // kernel's static LDS is below 1 KB.
-  static constexpr size_t fixed = plane_bytes + 1024;
-  static constexpr int waves2 = fixed + tab_bytes(8) <= kLdsMax / 2   ? 8
-                                : fixed + tab_bytes(6) <= kLdsMax / 2 ? 6
-                                : fixed + tab_bytes(4) <= kLdsMax / 2 ? 4
-                                                                      : 0;
-  static constexpr int waves = waves2                               ? waves2
-                               : fixed + tab_bytes(16) <= kLdsMax   ? 16
-                               : fixed + tab_bytes(12) <= kLdsMax   ? 12
-                                                                    : 8;
+  // the other's products), else one block of as many waves as fit.
+  static constexpr int waves2 = need(8) <= kLdsMax / 2 ? 8 : need(6) <= kLdsMax / 2 ? 6 : need(4) <= kLdsMax / 2 ? 4 : 0;
+  static constexpr int waves = waves2 ? waves2 : need(16) <= kLdsMax ? 16 : need(12) <= kLdsMax ? 12 : 8;
   static constexpr int threads = 64 * waves;
-  static constexpr int items = NR * (KS / 2);  // staged pairs of i2 slots
+  static constexpr int items = nrow * (KS / 2);  // staged pairs of i2 slots
   static constexpr int KB = (items + threads - 1) / threads;
   static constexpr size_t lds = plane_bytes + tab_bytes(waves);
 };
@@ -191,13 +190,13 @@ __global__ __launch_bounds__(GatherShape<Q2>::threads) void k_gather_mfma(const 
   using Sh = GatherShape<Q2>;
   constexpr int q = Q2 / 2, X = Sh::X, X1p = Sh::X1p, NR = Sh::NR, S = Sh::S, KS = Sh::KS;
   constexpr int NW = Sh::waves, NT = Sh::threads;
-  constexpr int PS = NR * KS;           // halves per plane
+  constexpr int PS = Sh::PS;            // halves per plane
   constexpr int UR = (Q2 >= 10 && Q2 < 16) ? 2 : 1;  // row blocks in flight per wave (as registers allow)
   static_assert(X <= KS && KS <= kPlaneK, "box too long along dimension 2");
-  static_assert(Sh::lds + 1024 <= kLdsMax, "LDS budget");
+  static_assert(Sh::need(Sh::waves) <= kLdsMax, "LDS budget");
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  _Float16 *plane = (_Float16 *)smem;           // [4][NR][KS] + 8: re_hi, re_lo, im_hi, im_lo, pad
-  float *wtab = (float *)(plane + 4 * PS + 8);  // [NW][32 points][S]: w1 at [0, X1p)
+  _Float16 *plane = (_Float16 *)smem;              // [4][nrow][KS] + tail: re_hi, re_lo, im_hi, im_lo
+  float *wtab = (float *)(plane + 4 * PS + Sh::tail);  // [NW][32 points][S]: w1 at [0, X1p)
   __shared__ float red[NW];
   __shared__ int sidx[3][32];
 
@@ -212,8 +211,8 @@ __global__ __launch_bounds__(GatherShape<Q2>::threads) void k_gather_mfma(const 
     const int d = threadIdx.x / 32, i = threadIdx.x % 32;
     const int cd = d == 0 ? c0 : (d == 1 ? c1 : c2);
     sidx[d][i] = i < X ? stored_index(cd * 8 - q + 1 + i, d, g) : -1;
-  } else if (threadIdx.x < 104) {
-    plane[4 * PS + threadIdx.x - 96] = (_Float16)0.0f;  // the pad the last row's read runs into
+  } else if (threadIdx.x < 96 + Sh::tail) {
+    plane[4 * PS + threadIdx.x - 96] = (_Float16)0.0f;  // the tail the last row block's reads run into
   }
   __syncthreads();
   // 2. the box (with its zero padding) in registers, pairs of i2 slots per item
