@@ -291,7 +291,7 @@ sgl_status make_plan(Plan &p, const void *points) {
   // 4. gather work list: chunks of at most kChunk points of one tile
   std::vector<int32_t> ts(p.ntiles + 1);
   SGL_TRY(hipMemcpy(ts.data(), p.tile_start, ts.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
-  const int kChunk = 1024;
+  const int kChunk = 2048;
   std::vector<int32_t> ch, tc(p.ntiles + 1);
   for (int64_t t = 0; t < p.ntiles; ++t) {
     tc[t] = (int32_t)(ch.size() / 3);

@@ -107,11 +107,11 @@ def test_b48_m2e6_anisotropic_mixture_f32():
 
 
 def stage_points(seed):
-    """2000 Gaussian points plus 2600 points packed into one tile (more than
-    two chunks of 1024), at rho = 1.1 max r."""
+    """2000 Gaussian points plus 4500 points packed into one tile (three
+    chunks: the plan caps a chunk at 2048 points), at rho = 1.1 max r."""
     rng = np.random.default_rng(seed)
     a = wl.gaussian_points(2000, seed)
-    c = np.array([0.35, -0.2, 0.5]) + 1e-3 * rng.standard_normal((2600, 3))
+    c = np.array([0.35, -0.2, 0.5]) + 1e-3 * rng.standard_normal((4500, 3))
     return np.concatenate([a, c], axis=0)
 
 
