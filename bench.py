@@ -73,13 +73,13 @@ def fft_bytes(info, B, cb):
     """Algorithmic HBM bytes of the 3D FFT passes: each pass reads its nonzero
     input rows once and writes its needed output rows once.  The passes run
     along dimensions 1, 0, 2 (forward) and 2, 0, 1 (adjoint); eta and the
-    intermediates are FP64, the forward's grid is in the plan's precision, the
-    adjoint's (folded) grid FP64."""
+    intermediates are FP64, the grid (forward output, folded adjoint input) is
+    in the plan's precision."""
     n0, n1, n2 = 4 * B, 2 * B, 2 * B
     N2, E0, E1 = info["N2"], info["E0"], info["E1"]
     eta, t1, t2, grid = n0 * n1 * n2, n0 * E1 * n2, E0 * E1 * n2, E0 * E1 * N2
     return {"fft_A": 16 * (eta + t1), "fft_B": 16 * (t1 + t2), "fft_C": 16 * t2 + cb * grid,
-            "fft_Ch": 16 * (grid + t2), "fft_Bh": 16 * (t2 + t1), "fft_Ah": 16 * (t1 + eta)}
+            "fft_Ch": cb * grid + 16 * t2, "fft_Bh": 16 * (t2 + t1), "fft_Ah": 16 * (t1 + eta)}
 
 
 def cpu_baseline(B, pts, fh, y, seconds):

@@ -404,7 +404,7 @@ sgl_status nfft_adj(Plan &p, const void *f, void *eta, int eta_f64) {
   SGL_STAGE(SGL_STAGE_SCATTER, launch_scatter(p, f, p.bufX));
   if (p.gather_mode == 0) SGL_STAGE(SGL_STAGE_FOLD, launch_fold(p, p.bufX));
   // the folded grid is double; the direct scatter writes the plan's precision
-  const int grid_f64 = (p.gather_mode == 0 || p.prec == SGL_F64) ? 1 : 0;
+  const int grid_f64 = p.prec == SGL_F64;
   SGL_STAGE(SGL_STAGE_FFT_CH, launch_fft_pass(p, p.passCh, p.bufX, p.bufY, 2, 0, grid_f64, 1));
   SGL_STAGE(SGL_STAGE_FFT_BH, launch_fft_pass(p, p.passBh, p.bufY, p.bufZ, 0, 0, 1, 1));
   SGL_STAGE(SGL_STAGE_FFT_AH, launch_fft_pass(p, p.passAh, p.bufZ, eta, 1, 2, 1, eta_f64));

@@ -180,7 +180,7 @@ hipError_t launch_fft_pass(const Plan &p, const FftPass &fp, const void *in, voi
                            int in_f64, int out_f64);
 hipError_t launch_gather(const Plan &p, const void *grid, void *f);
 hipError_t launch_scatter(const Plan &p, const void *f, void *grid);
-hipError_t launch_fold(const Plan &p, void *grid);  // writes a double grid in both precisions
+hipError_t launch_fold(const Plan &p, void *grid);  // sums in FP64, writes the grid in the plan's precision
 hipError_t launch_ndft_forward(const Plan &p, const void *eta, void *f);
 hipError_t launch_ndft_adjoint(const Plan &p, const void *f, void *eta);
 

@@ -1075,16 +1075,15 @@ constexpr int kMaxCand = 256;
 // Sum of the staged window boxes into the stored grid: one workgroup per
 // block of F0 x F1 x F2 stored cells; every chunk whose tile's window box
 // overlaps the block is added in a fixed order (tiles, then chunks), so the
-// result does not depend on scheduling.  Each grid cell is written once, in
-// double precision: the adjoint FFT and the adjoint conversion that follow
-// amplify relative errors of the grid (the conversion tables grow with the
-// radial functions towards r = rho), so the FP32 mode keeps its boxes in
-// FP32 but sums and transforms them in FP64.
+// result does not depend on scheduling.  Each grid cell is summed in double
+// precision and written once in the plan's precision: the sum is rounded only
+// when finished, so every cell keeps its error relative to itself (as the
+// forward's grid does), and the adjoint FFT that follows computes in FP64.
 template <class R>
 __global__ __launch_bounds__(256) void k_fold_staging(const cplx<R> *__restrict__ staging,
                                                       const int32_t *__restrict__ tile_chunk,
                                                       Geom g, int F0, int F1, int F2,
-                                                      cplx<double> *__restrict__ grid) {
+                                                      cplx<R> *__restrict__ grid) {
   __shared__ int cand[3][kMaxCand];
   __shared__ int coff[3][kMaxCand];  // region index of the block's first cell
   __shared__ int ncand[3];
@@ -1158,7 +1157,7 @@ __global__ __launch_bounds__(256) void k_fold_staging(const cplx<R> *__restrict_
         }
       }
     }
-    grid[((size_t)(S[0] + u0) * g.E[1] + (S[1] + u1)) * g.E[2] + (S[2] + u2)] = cplx<double>{ar, ai};
+    grid[((size_t)(S[0] + u0) * g.E[1] + (S[1] + u1)) * g.E[2] + (S[2] + u2)] = cplx<R>{(R)ar, (R)ai};
   }
 }
 
@@ -1295,12 +1294,13 @@ hipError_t scatter_q(const Plan &p, const void *f, void *grid) {
 // dimension 2, so stored cell s lies in the boxes of the tiles
 // floor(s'/8) - k, k = 0, 1, 2, at box index (s' mod 8) + 8k < X (s' = s, or
 // s + q - 1 mod N2 in dimension 2).  One thread per stored cell sums those
-// boxes (all chunks of each tile, in order) in double precision; a wave covers
-// 64 consecutive cells of one row, whose box entries are contiguous.
+// boxes (all chunks of each tile, in order) in double precision and writes the
+// sum in the plan's precision; a wave covers 64 consecutive cells of one row,
+// whose box entries are contiguous.
 template <class R>
 __global__ __launch_bounds__(256) void k_fold_tiles8(const cplx<R> *__restrict__ staging,
                                                      const int32_t *__restrict__ tile_chunk, Geom g,
-                                                     cplx<double> *__restrict__ grid) {
+                                                     cplx<R> *__restrict__ grid) {
   const int64_t cell = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (cell >= (int64_t)g.E[0] * g.E[1] * g.E[2]) return;
   const int X = g.X[0];
@@ -1333,7 +1333,7 @@ __global__ __launch_bounds__(256) void k_fold_tiles8(const cplx<R> *__restrict__
       }
     }
   }
-  grid[cell] = cplx<double>{ar, ai};
+  grid[cell] = cplx<R>{(R)ar, (R)ai};
 }
 
 template <class R, int Q2>
@@ -1352,13 +1352,13 @@ hipError_t fold_r(const Plan &p, void *grid) {
       p.pruned[0] && p.pruned[1] && !p.pruned[2] && p.N[2] == 8 * p.T[2] && p.E[2] == p.N[2] && p.X[2] <= p.N[2]) {
     const int64_t cells = (int64_t)p.E[0] * p.E[1] * p.E[2];
     k_fold_tiles8<R><<<(unsigned)((cells + 255) / 256), 256, 0, p.stream>>>((const cplx<R> *)p.staging, p.tile_chunk,
-                                                                           g, (cplx<double> *)grid);
+                                                                           g, (cplx<R> *)grid);
     return hipGetLastError();
   }
   const int F0 = p.F[0], F1 = p.F[1], F2 = p.F[2];
   const int64_t nb = (int64_t)((p.E[0] + F0 - 1) / F0) * ((p.E[1] + F1 - 1) / F1) * ((p.E[2] + F2 - 1) / F2);
   k_fold_staging<R><<<(unsigned)nb, 256, 0, p.stream>>>((const cplx<R> *)p.staging, p.tile_chunk, g, F0, F1, F2,
-                                                        (cplx<double> *)grid);
+                                                        (cplx<R> *)grid);
   return hipGetLastError();
 }
 
