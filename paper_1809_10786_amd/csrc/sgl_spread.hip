@@ -1301,16 +1301,18 @@ template <class R>
 __global__ __launch_bounds__(256) void k_fold_tiles8(const cplx<R> *__restrict__ staging,
                                                      const int32_t *__restrict__ tile_chunk, Geom g,
                                                      cplx<R> *__restrict__ grid) {
-  const int64_t cell = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (cell >= (int64_t)g.E[0] * g.E[1] * g.E[2]) return;
+  // a thread takes the two cells s' = 2u, 2u + 1 of one row: in every box they
+  // lie in the same tile, so the chunk ranges are shared and their entries are
+  // adjacent
+  const int64_t pair = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int half = g.E[2] / 2;
+  if (pair >= (int64_t)g.E[0] * g.E[1] * half) return;
   const int X = g.X[0];
   const size_t ncell = (size_t)X * X * X;
-  const int s2 = (int)(cell % g.E[2]);
-  const int r = (int)(cell / g.E[2]);
+  const int sp2 = 2 * (int)(pair % half);  // even; sp2 + 1 is in the same block of 8
+  const int r = (int)(pair / half);
   const int s1 = r % g.E[1], s0 = r / g.E[1];
-  int sp2 = s2 + g.q - 1;
-  if (sp2 >= g.N[2]) sp2 -= g.N[2];
-  double ar = 0.0, ai = 0.0;
+  double ar0 = 0.0, ai0 = 0.0, ar1 = 0.0, ai1 = 0.0;
   for (int k0 = 0; k0 < 3; ++k0) {
     const int c0 = (s0 >> 3) - k0, i0 = (s0 & 7) + 8 * k0;
     if (c0 < 0 || c0 >= g.T[0] || i0 >= X) continue;
@@ -1318,22 +1320,36 @@ __global__ __launch_bounds__(256) void k_fold_tiles8(const cplx<R> *__restrict__
       const int c1 = (s1 >> 3) - k1, i1 = (s1 & 7) + 8 * k1;
       if (c1 < 0 || c1 >= g.T[1] || i1 >= X) continue;
       for (int k2 = 0; k2 < 3; ++k2) {
-        const int i2 = (sp2 & 7) + 8 * k2;
+        const int i2 = (sp2 & 7) + 8 * k2;  // the second cell's is i2 + 1
         if (i2 >= X) continue;
+        const bool second = i2 + 1 < X;
         int c2 = (sp2 >> 3) - k2;
         if (c2 < 0) c2 += g.T[2];
         const int tile = (c0 * g.T[1] + c1) * g.T[2] + c2;
         const int ch0 = tile_chunk[tile], ch1 = tile_chunk[tile + 1];
         const size_t off = ((size_t)i0 * X + i1) * X + i2;
         for (int ch = ch0; ch < ch1; ++ch) {
-          const cplx<R> v = staging[(size_t)ch * ncell + off];
-          ar += v.re;
-          ai += v.im;
+          const cplx<R> *b = staging + (size_t)ch * ncell + off;
+          const cplx<R> v0 = b[0];
+          ar0 += v0.re;
+          ai0 += v0.im;
+          if (second) {
+            const cplx<R> v1 = b[1];
+            ar1 += v1.re;
+            ai1 += v1.im;
+          }
         }
       }
     }
   }
-  grid[cell] = cplx<R>{(R)ar, (R)ai};
+  // stored cells s = s' - q + 1 (mod N2)
+  int s2 = sp2 - (g.q - 1);
+  if (s2 < 0) s2 += g.N[2];
+  int s2b = s2 + 1;
+  if (s2b >= g.N[2]) s2b -= g.N[2];
+  const size_t row = ((size_t)s0 * g.E[1] + s1) * g.E[2];
+  grid[row + s2] = cplx<R>{(R)ar0, (R)ai0};
+  grid[row + s2b] = cplx<R>{(R)ar1, (R)ai1};
 }
 
 template <class R, int Q2>
@@ -1350,8 +1366,8 @@ hipError_t fold_r(const Plan &p, void *grid) {
   const Geom g = make_geom(p);
   if (p.L[0] == 8 && p.L[1] == 8 && p.L[2] == 8 && p.X[0] == p.X[1] && p.X[1] == p.X[2] && p.X[0] <= 24 &&
       p.pruned[0] && p.pruned[1] && !p.pruned[2] && p.N[2] == 8 * p.T[2] && p.E[2] == p.N[2] && p.X[2] <= p.N[2]) {
-    const int64_t cells = (int64_t)p.E[0] * p.E[1] * p.E[2];
-    k_fold_tiles8<R><<<(unsigned)((cells + 255) / 256), 256, 0, p.stream>>>((const cplx<R> *)p.staging, p.tile_chunk,
+    const int64_t pairs = (int64_t)p.E[0] * p.E[1] * (p.E[2] / 2);
+    k_fold_tiles8<R><<<(unsigned)((pairs + 255) / 256), 256, 0, p.stream>>>((const cplx<R> *)p.staging, p.tile_chunk,
                                                                            g, (cplx<R> *)grid);
     return hipGetLastError();
   }
