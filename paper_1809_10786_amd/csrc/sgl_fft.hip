@@ -176,7 +176,9 @@ __global__ __launch_bounds__(256) void k_fft(const cplx<Ri> *__restrict__ in, cp
     ic_base = 0;
   }
 
-  for (int e = threadIdx.x; e < L * W; e += blockDim.x) buf0[e] = cplx<R>{0, 0};
+  // zero the positions no input row lands on (the input's zero padding)
+  for (int e = threadIdx.x; e < (L - fp.nin) * W; e += blockDim.x)
+    buf0[wrap(fp.in_off + fp.nin + e / W, L) * W + e % W] = cplx<R>{0, 0};
   __syncthreads();
 
   for (int e = threadIdx.x; e < fp.nin * W; e += blockDim.x) {
@@ -344,7 +346,9 @@ __global__ __launch_bounds__((p2_threads<double, LOG2L, STRIDED>())) void k_fft_
     const int ic = STRIDED ? ic_base + (int)threadIdx.x : 0;
     linefac[threadIdx.x] = o < fp.outer && ic < fp.inner ? dc_line(dc, fp.axis, o, ic, n0, n1, n2) : 0.0;
   }
-  for (int e = threadIdx.x; e < L * SW; e += NT) buf[e] = cplx<R>{0, 0};
+  // zero the positions no input row lands on (the input's zero padding)
+  for (int e = threadIdx.x; e < (L - fp.nin) * SW; e += NT)
+    buf[((fp.in_off + fp.nin + e / SW) & (L - 1)) * SW + e % SW] = cplx<R>{0, 0};
   __syncthreads();
 
   for (int e = threadIdx.x; e < fp.nin * W; e += NT) {
