@@ -24,6 +24,10 @@
 //    in LDS; each workgroup owns a block of stored cells, accumulates in LDS
 //    the contributions of every point whose taps reach the block, and writes
 //    the block once.
+//  * FP32 plans with tiles of 8^3 cells use the matrix-core forms instead
+//    (k_gather_mfma, k_spread_mfma): the dimension-2 contraction of the gather
+//    and the contraction over the points of the scatter run as FP16 hi/lo
+//    products with FP32 accumulation; the staging and fold are shared.
 #include <type_traits>
 
 #include "sgl_internal.h"
