@@ -149,10 +149,16 @@ def stage_kernels(info):
 
 
 def source_digest(kernel):
+    """Digest of the kernel's source file with comments and whitespace removed,
+    so that a profile stays valid across edits of comments only."""
     import hashlib
+    import re
 
     path = os.path.join(ROOT, "paper_1809_10786_amd", "csrc", KERNEL_SOURCE.get(kernel, "sgl_spread.hip"))
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+    text = open(path).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return hashlib.sha256("".join(text.split()).encode()).hexdigest()[:16]
 
 
 def summarize_profiles(kt_dir, fetch_dir, write_dir, out_md, command):
