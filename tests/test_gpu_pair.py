@@ -1,8 +1,8 @@
 """sgl_forward_adjoint: the forward and the adjoint of one plan running
 concurrently on two streams give exactly (bit for bit) what sgl_forward and
 sgl_adjoint give, over repeated calls with new inputs, with profiling on (one
-stream) and on a plan whose stream is not the default one; overlapping
-buffers are rejected."""
+stream), on a plan whose stream is not the default one and in exact-NDFT
+mode; overlapping buffers are rejected."""
 import numpy as np
 import pytest
 
@@ -16,16 +16,18 @@ def say(*a):
     print(*a, flush=True)
 
 
-@pytest.mark.parametrize("B,M,prec,own_stream", [(32, 100_000, "f32", False), (8, 5_001, "f64", True),
-                                                  (64, 300_000, "f32", True)])
-def test_forward_adjoint_equals_separate_calls(B, M, prec, own_stream):
+@pytest.mark.parametrize("B,M,prec,own_stream,ndft", [(32, 100_000, "f32", False, False),
+                                                       (8, 5_001, "f64", True, False),
+                                                       (64, 300_000, "f32", True, False),
+                                                       (6, 2_000, "f64", False, True)])
+def test_forward_adjoint_equals_separate_calls(B, M, prec, own_stream, ndft):
     import paper_1809_10786_amd as sgl
 
-    say(f"forward_adjoint B={B} M={M} {prec} own_stream={own_stream}")
+    say(f"forward_adjoint B={B} M={M} {prec} own_stream={own_stream} exact_ndft={ndft}")
     rt, ct = (torch.float64, torch.complex128) if prec == "f64" else (torch.float32, torch.complex64)
     P = torch.from_numpy(wl.mixed_points(M, 500)).to("cuda", rt)
     stream = torch.cuda.Stream() if own_stream else None
-    plan = sgl.Plan(P, B, precision=prec, stream=stream)
+    plan = sgl.Plan(P, B, precision=prec, stream=stream, exact_ndft=ndft)
     with torch.cuda.stream(plan.stream):
         for rep in range(3):
             fh = torch.from_numpy(wl.coefficients(B, 510 + rep)).to("cuda", ct)
