@@ -164,15 +164,18 @@ sgl_status setup_geometry(Plan &p) {
     }
     p.NB[j] = (j < 2) ? p.N[j] / 2 + 1 : p.N[j];
   }
-  // gather tiles: the largest edges (<= 8) whose window box fits in LDS
+  // gather tiles: the largest edges (<= 8) whose window box fits in LDS: 120 KB
+  // for FP64 boxes (a workgroup may hold 160 KB on gfx950), 64 KB for FP32 ones
+  // (the matrix-core kernels stage their own FP16 planes)
   const size_t cb = cbytes(p);
+  const size_t kBoxBudget = (p.prec == SGL_F64 ? 120 : 64) * 1024;
   int L[3] = {8, 8, 8};
   auto box = [&](const int *l) { return (size_t)(l[0] + 2 * p.q - 1) * (l[1] + 2 * p.q - 1) * (l[2] + 2 * p.q - 1) * cb; };
-  while (box(L) > kLdsBudget && (L[0] > 4 || L[1] > 4 || L[2] > 4)) {
+  while (box(L) > kBoxBudget && (L[0] > 4 || L[1] > 4 || L[2] > 4)) {
     int j = (L[0] >= L[1] && L[0] >= L[2]) ? 0 : (L[1] >= L[2] ? 1 : 2);
     L[j] /= 2;
   }
-  p.gather_mode = box(L) <= kLdsBudget ? 0 : 1;
+  p.gather_mode = box(L) <= kBoxBudget ? 0 : 1;
   // the row-register spreading of the tiled scatter needs one thread per box
   // row (at most 512) and a box edge of 4 or 8 base cells along dimension 2
   if ((size_t)(L[0] + 2 * p.q - 1) * (L[1] + 2 * p.q - 1) > 512 || p.q > 8 || (L[2] != 4 && L[2] != 8))
