@@ -54,12 +54,19 @@ def parse():
                     help="MiB copied by a plain device copy before the timed region (counter calibration)")
     ap.add_argument("--summarize", nargs=3, metavar=("KT_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="summarize rocprofv3 output directories into --summary-out and exit")
-    ap.add_argument("--summary-out", default=os.path.join(ROOT, "profiles", "nfsglft_b64_m4e6_f32.md"))
+    ap.add_argument("--summary-out", default=None,
+                    help="summary file (default profiles/nfsglft_<workload>.md)")
     return ap.parse_args()
 
 
-PROFILE_COMMAND = ("rocprofv3 {mode} -T -f csv -d gpurun_out/prof_{tag} -o {tag} -- python3 bench.py --steps {steps} "
+PROFILE_COMMAND = ("rocprofv3 {mode} -T -f csv -d gpurun_out/prof_{tag} -o {tag} -- python3 bench.py {workload}--steps {steps} "
                    "--warmup 1 --no-cpu-baseline --check-points 0 --copy-calibration 256 --sequential")
+
+
+def profile_command(workload, **kw):
+    """The rocprofv3 command line of one profiled run of this script."""
+    wa = "" if workload == "b64_m4e6_f32" else f"--workload {workload} "
+    return PROFILE_COMMAND.format(workload=wa, **kw)
 
 
 def spread_flops(q):
@@ -134,7 +141,6 @@ def accuracy(B, plan, pts_used, fh_used, f_gpu, y, prec, m, torch, cdt):
 
 STAGE_KERNEL_VALU = {"gather": "k_gather_tiled", "scatter": "k_spread_rows", "fold": "k_fold_staging"}
 STAGE_KERNEL_MFMA = {"gather": "k_gather_mfma", "scatter": "k_spread_mfma", "fold": "k_fold_tiles8"}
-STAGE_KERNEL = dict(STAGE_KERNEL_MFMA)  # kernels of the benchmarked FP32 workload
 KERNEL_SOURCE = {"k_gather_tiled": "sgl_spread.hip", "k_spread_rows": "sgl_spread.hip",
                  "k_fold_staging": "sgl_spread.hip", "k_gather_mfma": "sgl_spread.hip",
                  "k_spread_mfma": "sgl_spread.hip", "k_fold_tiles8": "sgl_spread.hip", "k_fft": "sgl_fft.hip"}
@@ -161,7 +167,7 @@ def source_digest(kernel):
     return hashlib.sha256("".join(text.split()).encode()).hexdigest()[:16]
 
 
-def summarize_profiles(kt_dir, fetch_dir, write_dir, out_md, command):
+def summarize_profiles(kt_dir, fetch_dir, write_dir, out_md, workload):
     """Write a markdown summary of one rocprofv3 kernel-trace/stats run and two
     counter runs (FETCH_SIZE, WRITE_SIZE) of this script.  The counters are
     scaled by what they read for the plain 256 MiB device copy that the
@@ -188,10 +194,11 @@ def summarize_profiles(kt_dir, fetch_dir, write_dir, out_md, command):
             per.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]) * factor * 1024)
         counters[name] = (factor, {k: sum(v) / len(v) for k, v in per.items()})
     lines = [f"# rocprofv3 summary: {os.path.basename(out_md)[:-3]}", "",
-             "Command (kernel trace and statistics):", "", "```", command.format(mode="--kernel-trace --stats", tag="kt", steps=5),
+             "Command (kernel trace and statistics):", "", "```",
+             profile_command(workload, mode="--kernel-trace --stats", tag="kt", steps=5),
              "```", "", "Counter runs (one counter each):", "", "```",
-             command.format(mode="--pmc FETCH_SIZE", tag="fetch", steps=2),
-             command.format(mode="--pmc WRITE_SIZE", tag="write", steps=2),
+             profile_command(workload, mode="--pmc FETCH_SIZE", tag="fetch", steps=2),
+             profile_command(workload, mode="--pmc WRITE_SIZE", tag="write", steps=2),
              "```", "",
              f"Counter calibration on the plain 256 MiB copy: FETCH_SIZE x {counters['FETCH_SIZE'][0]:.3f}, "
              f"WRITE_SIZE x {counters['WRITE_SIZE'][0]:.3f} (scaled bytes below).", "",
@@ -207,7 +214,7 @@ def summarize_profiles(kt_dir, fetch_dir, write_dir, out_md, command):
                      f"{'' if rd is None else f'{rd / 1e6:.1f}'} | {'' if wr is None else f'{wr / 1e6:.1f}'} | "
                      f"{'' if gbs is None else f'{gbs:.0f}'} |")
     lines += ["", "Machine-readable (bytes per launch, with the digest of the kernel's source file):", ""]
-    for k in STAGE_KERNEL.values():
+    for k in list(STAGE_KERNEL_MFMA.values()) + list(STAGE_KERNEL_VALU.values()):
         rd = counters["FETCH_SIZE"][1].get(k)
         wr = counters["WRITE_SIZE"][1].get(k)
         if rd is not None and wr is not None:
@@ -384,11 +391,12 @@ def bench_batch(a, torch, wl, sgl):
 def main():
     a = parse()
     if a.summarize:
-        summarize_profiles(*a.summarize, out_md=a.summary_out, command=PROFILE_COMMAND)
+        out = a.summary_out or os.path.join(ROOT, "profiles", f"nfsglft_{a.workload}.md")
+        summarize_profiles(*a.summarize, out_md=out, workload=a.workload)
         return
     if a.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported by this build "
-              "(the transform shards over points, see DESIGN.md)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported "
+              "(sharding over points is a design, not an implementation)", file=sys.stderr)
         sys.exit(2)
     import torch
 

@@ -854,7 +854,9 @@ sgl_status sgl_forward_adjoint(sgl_plan_t plan, const void *fhat_dev, void *f_de
   Plan &a = plan->adj;
   SGL_TRY(hipEventRecord(plan->fork, p.stream));
   SGL_TRY(hipStreamWaitEvent(a.stream, plan->fork, 0));
+  p.gather_narrow = true;  // the adjoint's scatter shares the CUs
   st = plan_forward(p, fhat_dev, f_dev);
+  p.gather_narrow = false;
   const sgl_status sa = plan_adjoint(a, y_dev, ghat_dev);
   // the caller's stream waits for the adjoint, whatever happened on either side
   const hipError_t e1 = hipEventRecord(plan->join, a.stream);
