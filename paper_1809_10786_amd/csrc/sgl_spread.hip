@@ -70,7 +70,7 @@ __device__ inline R gauss(R d, R inv2lam) {
 // give the same bits.
 template <int Q2>
 struct GatherTiled {
-  static constexpr int threads = Q2 <= 16 ? 1024 : 256;
+  static constexpr int threads = Q2 <= 12 ? 1024 : Q2 <= 16 ? 512 : 256;
 };
 constexpr int kGatherSplit = 4;
 
@@ -96,9 +96,15 @@ __global__ __launch_bounds__(GatherTiled<Q2>::threads) void k_gather_tiled(const
     const int i2 = e % X2, r = e / X2, i1 = r % X1, i0 = r / X1;
     const int s0 = stored_index(wb0 + i0, 0, g), s1 = stored_index(wb1 + i1, 1, g),
               s2 = stored_index(wb2 + i2, 2, g);
-    cplx<R> v = {0, 0};
-    if (s0 >= 0 && s1 >= 0 && s2 >= 0) v = grid[((size_t)s0 * g.E[1] + s1) * g.E[2] + s2];
-    tile[e] = v;
+    // two scalars rather than a conditionally assigned pair, which the
+    // compiler kept in scratch memory for FP64
+    R vr = 0, vi = 0;
+    if (s0 >= 0 && s1 >= 0 && s2 >= 0) {
+      const cplx<R> v = grid[((size_t)s0 * g.E[1] + s1) * g.E[2] + s2];
+      vr = v.re;
+      vi = v.im;
+    }
+    tile[e] = cplx<R>{vr, vi};
   }
   __syncthreads();
   // the S lanes of a group are adjacent and share k, so a group is active or
