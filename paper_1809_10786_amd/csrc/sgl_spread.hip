@@ -842,12 +842,16 @@ __global__ __launch_bounds__(512) void k_spread_rows(const cplx<R> *__restrict__
     }
     __syncthreads();
     if (has_row) {
+      // the table reads of a point do not depend on the footprint test (the
+      // indices are clamped), so that those of the next points can be issued
+      // before this point's multiply-adds
+#pragma unroll 4
       for (int pi = 0; pi < nb; ++pi) {
         const int o = so[pi];
         const int t0 = i0 - (o & 255), t1 = i1 - (o >> 8);
+        const R w01 = sw0[pi][min(max(t0, 0), Q2 - 1)] * sw1[pi][min(max(t1, 0), Q2 - 1)];
+        const cplx<R> yv = sy[pi];
         if ((unsigned)t0 < (unsigned)Q2 && (unsigned)t1 < (unsigned)Q2) {
-          const R w01 = sw0[pi][t0] * sw1[pi][t1];
-          const cplx<R> yv = sy[pi];
           const R cr = yv.re * w01, ci = yv.im * w01;
 #pragma unroll
           for (int c = 0; c < X2; ++c) {
