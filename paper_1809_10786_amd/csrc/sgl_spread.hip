@@ -1377,14 +1377,23 @@ __global__ __launch_bounds__(256) void k_fold_tiles8(const cplx<R> *__restrict__
     for (int k1 = 0; k1 < 3; ++k1) {
       const int c1 = (s1 >> 3) - k1, i1 = (s1 & 7) + 8 * k1;
       if (c1 < 0 || c1 >= g.T[1] || i1 >= X) continue;
+      // the chunk ranges of the three tiles along dimension 2 are looked up
+      // before any box is read (every tile index is valid)
+      int cr0[3], cr1[3];
+#pragma unroll
+      for (int k2 = 0; k2 < 3; ++k2) {
+        int c2 = (sp2 >> 3) - k2;
+        if (c2 < 0) c2 += g.T[2];
+        const int tile = (c0 * g.T[1] + c1) * g.T[2] + c2;
+        cr0[k2] = tile_chunk[tile];
+        cr1[k2] = tile_chunk[tile + 1];
+      }
+#pragma unroll
       for (int k2 = 0; k2 < 3; ++k2) {
         const int i2 = (sp2 & 7) + 8 * k2;  // the second cell's is i2 + 1
         if (i2 >= X) continue;
         const bool second = i2 + 1 < X;
-        int c2 = (sp2 >> 3) - k2;
-        if (c2 < 0) c2 += g.T[2];
-        const int tile = (c0 * g.T[1] + c1) * g.T[2] + c2;
-        const int ch0 = tile_chunk[tile], ch1 = tile_chunk[tile + 1];
+        const int ch0 = cr0[k2], ch1 = cr1[k2];
         const size_t off = ((size_t)i0 * X + i1) * X + i2;
         for (int ch = ch0; ch < ch1; ++ch) {
           const cplx<R> *b = staging + (size_t)ch * ncell + off;
