@@ -112,8 +112,8 @@ struct Plan {
   int L[3], T[3], NB[3], X[3];
   int64_t ntiles = 0;
   int gather_mode = 0;  // 0: LDS tiles, 1: direct from the grid
-  // tiled gather in 256-thread workgroups, one lane per point, leaving room on
-  // each CU for the workgroups of a concurrent scatter
+  // tiled gather in 256-thread workgroups, leaving room on each CU for the
+  // workgroups of a concurrent scatter
   bool gather_narrow = false;
   int mfma = 0;         // FP32, 8^3 tiles, q <= 8: matrix-core gather and spread
   // scatter output blocks over stored cells

@@ -59,15 +59,13 @@ __device__ inline R gauss(R d, R inv2lam) {
 
 // ---------------------------------------------------------------- gather, tiled
 
-// Threads of a tiled-gather workgroup, and lanes that share one point.  The
-// dimension-0 planes of a point fall into four classes t0 mod 4 with partial
-// sums p0..p3, always combined as (p0 + p1) + (p2 + p3).  With split 4, lane
-// `sub` of a group of four adjacent lanes computes p_sub and the group adds
-// them with two butterfly exchanges, so that small chunks still keep many
-// lanes busy and the box in LDS is read by 16 waves per CU instead of 4.  With
-// split 1 (256 threads, one lane per point) the lane computes all four, which
-// leaves registers for a scatter running beside it on the same CU; both forms
-// give the same bits.
+// Threads of a tiled-gather workgroup, and lanes that share one point: lane
+// `sub` of a group of four adjacent lanes takes the dimension-0 planes
+// t0 = sub, sub + 4, ... and the group adds the four partial sums as
+// (p0 + p1) + (p2 + p3) with two butterfly exchanges.  Small chunks still keep
+// many lanes busy, and 1,024-thread workgroups read the box in LDS with 16
+// waves per CU.  The narrow form (256 threads) leaves registers for a scatter
+// running beside it on the same CU; the sums, and so the bits, are the same.
 template <int Q2>
 struct GatherTiled {
   static constexpr int threads = Q2 <= 12 ? 1024 : Q2 <= 16 ? 512 : 256;
@@ -79,11 +77,11 @@ __global__ __launch_bounds__(GatherTiled<Q2>::threads) void k_gather_tiled(const
                                                       const PointRec<R> *__restrict__ pts,
                                                       const int32_t *__restrict__ perm,
                                                       const int32_t *__restrict__ chunks, Geom g, R inv2lam,
-                                                      int split, cplx<R> *__restrict__ f) {
+                                                      cplx<R> *__restrict__ f) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   cplx<R> *tile = (cplx<R> *)smem;
   constexpr int q = Q2 / 2;
-  const int S = split;  // 1 or 4
+  constexpr int S = kGatherSplit;
   const int tidx = chunks[3 * blockIdx.x];
   const int start = chunks[3 * blockIdx.x + 1];
   const int count = chunks[3 * blockIdx.x + 2];
@@ -122,50 +120,32 @@ __global__ __launch_bounds__(GatherTiled<Q2>::threads) void k_gather_tiled(const
       w2[t] = gauss<R>(pr.frac[2] + (R)(q - 1 - t), inv2lam);
     }
     const cplx<R> *base = tile + ((size_t)o0 * X1 + o1) * X2 + o2;
-    R ar = 0, ai = 0;  // p_j of the class in hand, then the point's sum
-    R er = 0, ei = 0;  // p0 or p2 (split 1)
-    R hr = 0, hi = 0;  // p0 + p1 (split 1)
-    for (int j = sub; j < 4; j += S) {
-      ar = ai = 0;
-      for (int t0 = j; t0 < Q2; t0 += 4) {
-        const R w0 = gauss<R>(pr.frac[0] + (R)(q - 1 - t0), inv2lam);
-        const cplx<R> *plane = base + (size_t)t0 * X1 * X2;
-        R br = 0, bi = 0;
+    R ar = 0, ai = 0;
+    for (int t0 = sub; t0 < Q2; t0 += S) {
+      const R w0 = gauss<R>(pr.frac[0] + (R)(q - 1 - t0), inv2lam);
+      const cplx<R> *plane = base + (size_t)t0 * X1 * X2;
+      R br = 0, bi = 0;
 #pragma unroll
-        for (int t1 = 0; t1 < Q2; ++t1) {
-          const cplx<R> *row = plane + t1 * X2;
-          R cr = 0, ci = 0;
+      for (int t1 = 0; t1 < Q2; ++t1) {
+        const cplx<R> *row = plane + t1 * X2;
+        R cr = 0, ci = 0;
 #pragma unroll
-          for (int t2 = 0; t2 < Q2; ++t2) {
-            const cplx<R> v = row[t2];
-            cr += w2[t2] * v.re;
-            ci += w2[t2] * v.im;
-          }
-          br += w1[t1] * cr;
-          bi += w1[t1] * ci;
+        for (int t2 = 0; t2 < Q2; ++t2) {
+          const cplx<R> v = row[t2];
+          cr += w2[t2] * v.re;
+          ci += w2[t2] * v.im;
         }
-        ar += w0 * br;
-        ai += w0 * bi;
+        br += w1[t1] * cr;
+        bi += w1[t1] * ci;
       }
-      if (S == 1) {
-        if ((j & 1) == 0) {
-          er = ar;
-          ei = ai;
-        } else if (j == 1) {
-          hr = er + ar;
-          hi = ei + ai;
-        } else {
-          ar = hr + (er + ar);
-          ai = hi + (ei + ai);
-        }
-      }
+      ar += w0 * br;
+      ai += w0 * bi;
     }
-    if (S == 4) {  // (p0 + p1) + (p2 + p3) in every lane of the group
-      ar += __shfl_xor(ar, 1, 64);
-      ai += __shfl_xor(ai, 1, 64);
-      ar += __shfl_xor(ar, 2, 64);
-      ai += __shfl_xor(ai, 2, 64);
-    }
+    // (p0 + p1) + (p2 + p3) in every lane of the group
+    ar += __shfl_xor(ar, 1, 64);
+    ai += __shfl_xor(ai, 1, 64);
+    ar += __shfl_xor(ar, 2, 64);
+    ai += __shfl_xor(ai, 2, 64);
     if (sub == 0) f[perm[k]] = cplx<R>{ar, ai};
   }
 }
@@ -1305,8 +1285,7 @@ hipError_t gather_q(const Plan &p, const void *grid, void *f) {
     const size_t lds = (size_t)p.X[0] * p.X[1] * p.X[2] * sizeof(cplx<R>);
     const bool narrow = p.gather_narrow || GatherTiled<Q2>::threads == 256;
     k_gather_tiled<R, Q2><<<(unsigned)p.nchunks, narrow ? 256 : GatherTiled<Q2>::threads, lds, p.stream>>>(
-        (const cplx<R> *)grid, (const PointRec<R> *)p.pts, p.perm, p.chunks, g, inv2lam, narrow ? 1 : kGatherSplit,
-        (cplx<R> *)f);
+        (const cplx<R> *)grid, (const PointRec<R> *)p.pts, p.perm, p.chunks, g, inv2lam, (cplx<R> *)f);
   } else {
     k_gather_direct<R, Q2><<<(unsigned)((p.M + 255) / 256), 256, 0, p.stream>>>(
         (const cplx<R> *)grid, (const PointRec<R> *)p.pts, p.perm, p.M, g, inv2lam, (cplx<R> *)f);
