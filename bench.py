@@ -1,11 +1,13 @@
 """Throughput of the fast SGL Fourier transform for scattered data on one MI355X.
 
-One step = one forward (f = Lambda fhat) plus one adjoint (fhat = Lambda^H y)
-over the whole workload, inputs resident in HBM.  Default workload: B=64,
-M=4e6 points iid N(0, I/2), coefficients with n^-1.5 decay, FP32, sigma=2,
-q=6.  Prints one JSON line with points/s, the roofline position of the
-dominant kernel (HIP-event time on the plan's stream), the accuracy against
-the direct-sum oracle on a sampled subset, and the oracle's own CPU rate.
+One step = one forward (f = Lambda fhat) then one adjoint (fhat = Lambda^H y)
+over the whole workload on the plan's stream, inputs resident in HBM.
+Default workload: B=64, M=4e6 points iid N(0, I/2), coefficients with n^-1.5
+decay, FP64 arithmetic throughout (the paper's precision), sigma=2, q=6.
+Prints one JSON line with points/s, the roofline position of the dominant
+kernel (HIP-event time on the plan's stream), the accuracy against the
+direct-sum oracle on a sampled subset, the oracle's own CPU rate, and beside
+them the same workload in the FP32 form (matrix-core gather and spread).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
@@ -36,7 +38,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="b64_m4e6_f32")
+    ap.add_argument("--workload", default="b64_m4e6_f64")
+    ap.add_argument("--beside", nargs="*", default=["b64_m4e6_f32"],
+                    help="further workloads measured in the same run and reported beside the headline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--grad", action="store_true",
                     help="time the differentiation step (forward, adjoint and point gradient) instead")
@@ -47,7 +51,7 @@ def parse():
     ap.add_argument("--conv-split16", action="store_true",
                     help="conversion products on the FP16 matrix cores with hi/lo split operands")
     ap.add_argument("--sequential", action="store_true",
-                    help="time forward then adjoint on one stream instead of sgl_forward_adjoint")
+                    help="only the headline workload, without the concurrent paired call (profiled runs)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--check-points", type=int, default=2000)
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -65,15 +69,14 @@ PROFILE_COMMAND = ("rocprofv3 {mode} -T -f csv -d gpurun_out/prof_{tag} -o {tag}
 
 def profile_command(workload, **kw):
     """The rocprofv3 command line of one profiled run of this script."""
-    wa = "" if workload == "b64_m4e6_f32" else f"--workload {workload} "
+    wa = "" if workload == "b64_m4e6_f64" else f"--workload {workload} "
     return PROFILE_COMMAND.format(workload=wa, **kw)
 
 
 def spread_flops(q):
-    """Algorithmic flops per point of the windowed gather (or scatter): (2q)^3
-    complex-by-real multiply-adds (4 flop) for the separable sum."""
-    t = 2 * q
-    return 4 * (t ** 3 + t ** 2 + t)
+    """Algorithmic flops per point of the windowed gather (or scatter): the
+    (2q)^3 window taps, each a complex-by-real multiply-add (4 flop)."""
+    return 4 * (2 * q) ** 3
 
 
 def fft_bytes(info, B, cb):
@@ -289,7 +292,7 @@ def bench_inverse(a, torch, wl, sgl):
     """Inverse transform: CGNR to a normal residual of 1e-3 on noisy samples
     (1 % noise) with W = I, with histogram density weights and with learned
     weights (network trained on another cloud of the same distribution)."""
-    name = a.workload if a.workload != "b64_m4e6_f32" else "b32_m3e5_clustered_f64"
+    name = a.workload if a.workload != "b64_m4e6_f64" else "b32_m3e5_clustered_f64"
     w, pts, fh, _ = wl.workload(name, seed=0)
     B, M, q, prec = w["B"], w["M"], w["q"], w["prec"]
     rdt = torch.float64 if prec == "f64" else torch.float32
@@ -388,6 +391,132 @@ def bench_batch(a, torch, wl, sgl):
         "eager_ms_per_step": res["eager"], "graph_ms_per_step": ms}), flush=True)
 
 
+def measure(a, torch, wl, sgl, name, check_points, conv_split16=False, paired=True):
+    """Plan the workload, time K steps (forward then adjoint on the plan's
+    stream; also the concurrent paired call), time every stage with HIP events
+    on a second pass, and check sampled outputs against the oracle."""
+    w, pts, fh, y = wl.workload(name, seed=0)
+    B, M, q, prec = w["B"], w["M"], w["q"], w["prec"]
+    rdt = torch.float64 if prec == "f64" else torch.float32
+    cdt = torch.complex128 if prec == "f64" else torch.complex64
+    cb = 16 if prec == "f64" else 8
+    print(f"[bench] workload {name}: B={B} M={M} q={q} {prec}", file=sys.stderr, flush=True)
+
+    dpts = torch.from_numpy(pts).to("cuda", rdt)
+    dfh = torch.from_numpy(fh).to("cuda", cdt)
+    dy = torch.from_numpy(y).to("cuda", cdt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = sgl.Plan(dpts, B, sigma=w["sigma"], q=q, precision=prec, conv_split16=conv_split16)
+    torch.cuda.synchronize()
+    plan_ms = (time.perf_counter() - t0) * 1e3
+    del dpts
+    info = plan.info()
+    print(f"[bench] plan {plan_ms:.1f} ms, rho={plan.rho:.4f}, info={info}", file=sys.stderr, flush=True)
+
+    if a.copy_calibration > 0:
+        # a plain copy kernel of known size: reads and writes copy_calibration MiB each
+        src = torch.ones(a.copy_calibration * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        print(f"[bench] copy calibration: 3 x {a.copy_calibration} MiB", file=sys.stderr, flush=True)
+
+    f = torch.empty(M, dtype=cdt, device="cuda")
+    g = torch.empty(plan.nc, dtype=cdt, device="cuda")
+    for _ in range(a.warmup):
+        plan.forward(dfh, out=f)
+        plan.adjoint(dy, out=g)
+        if paired:
+            plan.forward_adjoint(dfh, dy, out=f, out_adj=g)  # the first call sets up the second stream
+    torch.cuda.synchronize()
+    print("[bench] warmup done", file=sys.stderr, flush=True)
+
+    def timed(fn):
+        """Mean ms per step over exactly K steps (host clock, synchronised on
+        both sides) and the median of the per-step HIP-event times (events at
+        the step boundaries on the plan's stream)."""
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(a.steps + 1)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev[0].record()
+        for k in range(a.steps):
+            fn()
+            ev[k + 1].record()
+        torch.cuda.synchronize()
+        mean = (time.perf_counter() - t0) * 1e3 / a.steps
+        per = sorted(ev[k].elapsed_time(ev[k + 1]) for k in range(a.steps))
+        return mean, per[len(per) // 2]
+
+    def sequential():
+        plan.forward(dfh, out=f)
+        plan.adjoint(dy, out=g)
+
+    # the step: forward then adjoint on the plan's stream (a dependent caller's
+    # order, as in CGNR), no stage timers
+    ms_seq, med_seq = timed(sequential)
+    ms_pair = med_pair = None
+    if paired:
+        # the same two transforms on independent inputs, run concurrently on two streams
+        ms_pair, med_pair = timed(lambda: plan.forward_adjoint(dfh, dy, out=f, out_adj=g))
+    # per-kernel durations: HIP events on the plan's stream over a second pass
+    # of the same K steps, one stage at a time
+    plan.profile(True)
+    plan.stage_times(reset=True)
+    timed(sequential)
+    stages = plan.stage_times(reset=True)
+    plan.profile(False)
+    print(f"[bench] {name} {a.steps} steps: forward then adjoint {ms_seq:.3f} ms/step (median {med_seq:.3f}), "
+          f"{M / (ms_seq * 1e-3):.4g} points/s" +
+          (f"; concurrent pair {ms_pair:.3f} ms/step" if paired else ""), file=sys.stderr, flush=True)
+
+    avg = {k: v[0] / v[1] for k, v in stages.items()}
+    print(f"[bench] stages (ms/launch): " + ", ".join(f"{k}={v:.4f}" for k, v in avg.items()), file=sys.stderr,
+          flush=True)
+    dom = max(avg, key=avg.get)
+    fb = fft_bytes(info, B, cb)
+    kern = stage_kernels(info)
+    if dom in ("gather", "scatter"):
+        # algorithmic flops per launch: 4 (2q)^3 per point (complex-by-real
+        # multiply-adds of the window taps) times the M points of one launch
+        flops = spread_flops(q) * M
+        achieved = flops / (avg[dom] * 1e-3) / 1e12
+        if info["gather_mode"] == 2:
+            # the contraction runs on the FP16 matrix cores (hi/lo split operands)
+            bound, peak = "mfma", MFMA_PEAK_F16_TFLOPS
+        else:
+            bound, peak = "alu", ALU_PEAK_F32_TFLOPS if prec == "f32" else ALU_PEAK_F64_TFLOPS
+        roof = {"kernel": kern[dom], "bound": bound, "achieved": achieved, "peak": peak,
+                "unit": "TFLOP/s", "frac": achieved / peak, "flop_per_point": spread_flops(q),
+                "launch_ms": avg[dom], "traffic": profiled_traffic(name, kern[dom])}
+        if prec == "f32":
+            roof["frac_of_fp32_vector_peak"] = achieved / ALU_PEAK_F32_TFLOPS
+    else:
+        byts = fb.get(dom, 0)
+        achieved = byts / (avg[dom] * 1e-3) / 1e9
+        roof = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "launch_ms": avg[dom], "traffic": None}
+    # HBM fraction of the whole step at algorithmic bytes
+    step_bytes = sum(fb.values()) + 2 * M * (cb + 16 + 4)
+    acc = None
+    if check_points > 0:
+        f_host = f.cpu().numpy().astype(np.complex128)
+        pts_used = pts.astype(np.float32).astype(np.float64) if prec == "f32" else pts
+        fh_used = fh.astype(np.complex64).astype(np.complex128) if prec == "f32" else fh
+        acc = accuracy(B, plan, pts_used, fh_used, f_host, y, prec, check_points, torch, cdt)
+        print(f"[bench] accuracy {acc}", file=sys.stderr, flush=True)
+    res = {"workload": name, "B": B, "M": M, "sigma": w["sigma"], "q": q, "prec": prec, "points": w["points"],
+           "coeff_decay": w["decay"], "rho": plan.rho, "plan_ms": plan_ms, "ms_seq": ms_seq,
+           "median_ms_seq": med_seq, "ms_pair": ms_pair, "median_ms_pair": med_pair,
+           "stages_ms": {k: round(v, 5) for k, v in avg.items()}, "roofline": roof,
+           "hbm_frac_step": step_bytes / (ms_seq * 1e-3) / (HBM_PEAK_GBS * 1e9), "rel_err": acc,
+           "inputs": (pts, fh, y)}
+    plan.close()
+    return res
+
+
 def main():
     a = parse()
     if a.summarize:
@@ -409,138 +538,54 @@ def main():
         return bench_inverse(a, torch, wl, sgl)
     if a.batch:
         return bench_batch(a, torch, wl, sgl)
-    w, pts, fh, y = wl.workload(a.workload, seed=0)
-    B, M, q, prec = w["B"], w["M"], w["q"], w["prec"]
-    rdt = torch.float64 if prec == "f64" else torch.float32
-    cdt = torch.complex128 if prec == "f64" else torch.complex64
-    cb = 16 if prec == "f64" else 8
-    print(f"[bench] workload {a.workload}: B={B} M={M} q={q} {prec}", file=sys.stderr, flush=True)
-
-    dpts = torch.from_numpy(pts).to("cuda", rdt)
-    dfh = torch.from_numpy(fh).to("cuda", cdt)
-    dy = torch.from_numpy(y).to("cuda", cdt)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    plan = sgl.Plan(dpts, B, sigma=w["sigma"], q=q, precision=prec, conv_split16=a.conv_split16)
-    torch.cuda.synchronize()
-    plan_ms = (time.perf_counter() - t0) * 1e3
-    info = plan.info()
-    print(f"[bench] plan {plan_ms:.1f} ms, rho={plan.rho:.4f}, info={info}", file=sys.stderr, flush=True)
-
-    if a.copy_calibration > 0:
-        # a plain copy kernel of known size: reads and writes copy_calibration MiB each
-        src = torch.ones(a.copy_calibration * (1 << 20) // 4, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-        print(f"[bench] copy calibration: 3 x {a.copy_calibration} MiB", file=sys.stderr, flush=True)
-
-    f = torch.empty(M, dtype=cdt, device="cuda")
-    g = torch.empty(plan.nc, dtype=cdt, device="cuda")
-    for _ in range(a.warmup):
-        plan.forward(dfh, out=f)
-        plan.adjoint(dy, out=g)
-        if not a.sequential:
-            plan.forward_adjoint(dfh, dy, out=f, out_adj=g)  # the first call sets up the second stream
-    torch.cuda.synchronize()
-    print("[bench] warmup done", file=sys.stderr, flush=True)
-
-    def timed(fn):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(a.steps):
-            fn()
-        torch.cuda.synchronize()
-        return (time.perf_counter() - t0) * 1e3 / a.steps
-
-    def sequential():
-        plan.forward(dfh, out=f)
-        plan.adjoint(dy, out=g)
-
-    # the step: forward and adjoint concurrently (sgl_forward_adjoint), no timers
-    ms_seq = timed(sequential)
-    ms_per_step = ms_seq if a.sequential else timed(lambda: plan.forward_adjoint(dfh, dy, out=f, out_adj=g))
-    # per-kernel durations: HIP events on the plan's stream over the same K steps,
-    # run one stage after the other so that every stage is timed on its own
-    plan.profile(True)
-    plan.stage_times(reset=True)
-    timed(sequential)
-    stages = plan.stage_times(reset=True)
-    plan.profile(False)
-    value = M / (ms_per_step / 1e3)
-    print(f"[bench] {a.steps} steps: {ms_per_step:.3f} ms/step, {value:.4g} points/s "
-          f"(forward then adjoint on one stream: {ms_seq:.3f} ms/step)", file=sys.stderr, flush=True)
-
-    # per-stage averages and the dominant kernel's roofline position
-    avg = {k: v[0] / v[1] for k, v in stages.items()}
-    dom = max(avg, key=avg.get)
-    fb = fft_bytes(info, B, cb)
-    kern = stage_kernels(info)
-    if dom in ("gather", "scatter"):
-        # algorithmic flops: (2q)^3 complex-by-real multiply-adds per point
-        flops = spread_flops(q) * M
-        achieved = flops / (avg[dom] * 1e-3) / 1e12
-        if info["gather_mode"] == 2:
-            # the contraction runs on the FP16 matrix cores (hi/lo split operands)
-            bound, peak = "mfma", MFMA_PEAK_F16_TFLOPS
-        else:
-            bound, peak = "alu", ALU_PEAK_F32_TFLOPS if prec == "f32" else ALU_PEAK_F64_TFLOPS
-        roof = {"kernel": kern[dom], "bound": bound, "achieved": achieved, "peak": peak,
-                "unit": "TFLOP/s", "frac": achieved / peak,
-                "frac_of_fp32_vector_peak": achieved / ALU_PEAK_F32_TFLOPS,
-                "traffic": profiled_traffic(a.workload, kern[dom])}
-    else:
-        byts = fb.get(dom, 0)
-        achieved = byts / (avg[dom] * 1e-3) / 1e9
-        roof = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None}
-    # HBM fraction of the whole step at algorithmic bytes
-    step_bytes = sum(fb.values()) + 2 * M * (cb + 16 + 4)
-    hbm_frac_step = step_bytes / (ms_per_step * 1e-3) / (HBM_PEAK_GBS * 1e9)
-    print(f"[bench] stages (ms/launch): " + ", ".join(f"{k}={v:.4f}" for k, v in avg.items()), file=sys.stderr,
-          flush=True)
-
-    f_host = f.cpu().numpy().astype(np.complex128)
-    pts_used = pts.astype(np.float32).astype(np.float64) if prec == "f32" else pts
-    fh_used = fh.astype(np.complex64).astype(np.complex128) if prec == "f32" else fh
-    acc = None
-    if a.check_points > 0:
-        acc = accuracy(B, plan, pts_used, fh_used, f_host, y, prec, a.check_points, torch, cdt)
-        print(f"[bench] accuracy {acc}", file=sys.stderr, flush=True)
+    r = measure(a, torch, wl, sgl, a.workload, a.check_points, conv_split16=a.conv_split16,
+                paired=not a.sequential)
+    pts, fh, y = r.pop("inputs")
+    # the same workload in the other forms, beside the headline
+    beside = {}
+    for extra in ([] if a.sequential else a.beside):
+        if extra == a.workload:
+            continue
+        e = measure(a, torch, wl, sgl, extra, min(a.check_points, 1000))
+        e.pop("inputs")
+        e["points_per_s"] = e["M"] / (e["ms_seq"] * 1e-3)
+        beside[extra] = e
 
     cpu = None
     if not a.no_cpu_baseline:
-        cpu = cpu_baseline(B, pts_used, fh_used, y.astype(np.complex128), a.cpu_seconds)
+        pts_used = pts.astype(np.float32).astype(np.float64) if r["prec"] == "f32" else pts
+        fh_used = fh.astype(np.complex64).astype(np.complex128) if r["prec"] == "f32" else fh
+        cpu = cpu_baseline(r["B"], pts_used, fh_used, y.astype(np.complex128), a.cpu_seconds)
         print(f"[bench] cpu baseline {cpu}", file=sys.stderr, flush=True)
 
+    ms = r["ms_seq"]
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": r["M"] / (ms * 1e-3),
         "unit": "points/s",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": ms,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": prec,
+        "dtype": r["prec"],
         "data": "synthetic",
-        "config": {"workload": a.workload, "B": B, "M": M, "sigma": w["sigma"], "q": q,
-                   "points": w["points"], "coeff_decay": w["decay"], "rho": plan.rho,
+        "config": {"workload": r["workload"], "B": r["B"], "M": r["M"], "sigma": r["sigma"], "q": r["q"],
+                   "points": r["points"], "coeff_decay": r["coeff_decay"], "rho": r["rho"],
                    "conversion": "fp16-split-mfma" if a.conv_split16 else "fp64"},
-        "roofline": roof,
-        "hbm_frac_step": hbm_frac_step,
+        "roofline": r["roofline"],
+        "hbm_frac_step": r["hbm_frac_step"],
         "cpu_baseline": cpu,
-        "rel_err": acc,
-        "step": "forward + adjoint on one stream" if a.sequential else
-                "sgl_forward_adjoint: forward and adjoint concurrently on two streams",
-        "ms_per_step_one_stream": ms_seq,
+        "rel_err": r["rel_err"],
+        "step": "forward then adjoint on the plan's stream",
+        "median_ms_per_step": r["median_ms_seq"],
+        "ms_per_step_concurrent_pair": r["ms_pair"],
         "stage_timing": "HIP events on the plan's stream over a second pass of the same steps, one stage at a time",
-        "stages_ms": {k: round(v, 5) for k, v in avg.items()},
-        "plan_ms": plan_ms,
+        "stages_ms": r["stages_ms"],
+        "plan_ms": r["plan_ms"],
+        "beside": beside,
     }
     print(json.dumps(out), flush=True)
 

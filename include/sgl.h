@@ -137,10 +137,12 @@ sgl_status sgl_nfft_adjoint(sgl_plan_t plan, const void *f_dev, void *eta_dev);
  * replaces the window, chained through x -> (r, theta, phi) -> x~ (eq. x_tilde)
  * -> u = N x~ / (2 pi).  fhat_dev: Nc complex; points_dev: the M x 3 points the
  * plan was made with (caller order, plan precision); g_dev: M complex; grad_dev:
- * M x 3 reals (plan precision), caller order.  Points on the z axis, at the
- * origin or with r >= rho get NaN (the angles are not differentiable there;
- * make the plan with rho slightly above max |x| to differentiate the outermost
- * point).  SGL_E_UNSUPPORTED with SGL_FLAG_EXACT_NDFT; SGL_E_INVAL for null or
+ * M x 3 reals (plan precision), caller order.  At r = rho (x~_0 = 0: the
+ * outermost point when the plan's rho is max |x|, eq. nfsglft_rho) the radial
+ * factor takes its limit through the second window derivative, since f
+ * depends on x~_0 only through cos x~_0 (the radial expansion of Section 6 is
+ * a cosine series).  Points on the z axis or at the origin get NaN (the
+ * angles of eq. x_tilde are not differentiable there).  SGL_E_UNSUPPORTED with SGL_FLAG_EXACT_NDFT; SGL_E_INVAL for null or
  * overlapping grad_dev.  Enqueued on the plan's stream. */
 sgl_status sgl_grad_points(sgl_plan_t plan, const void *fhat_dev, const void *points_dev, const void *g_dev,
                            void *grad_dev);
@@ -241,7 +243,10 @@ sgl_status sgl_mlp_train_step(sgl_plan_t plan, float *params_dev, float *m_dev, 
 sgl_status sgl_forward_adjoint(sgl_plan_t plan, const void *fhat_dev, void *f_dev, const void *y_dev,
                                void *ghat_dev);
 
-/* The rho the plan uses (host pointer out). */
+/* The rho the plan uses (host pointer out): the user's rho, or max_i |x_i|
+ * (eq. nfsglft_rho, Section 8) when the plan was made with rho <= 0, or 1 when
+ * every point is at the origin (then only l = 0 terms are nonzero and any
+ * rho > 0 is exact).  SGL_E_INVAL for a null plan or rho. */
 sgl_status sgl_plan_rho(sgl_plan_t plan, double *rho);
 
 /* Informational: number of points, FFT grid sigma*n, stored (pruned) grid
@@ -286,14 +291,18 @@ sgl_status sgl_plan_profile(sgl_plan_t plan, int32_t enable);
 sgl_status sgl_plan_stage_times(sgl_plan_t plan, double ms[SGL_NUM_STAGES], int64_t counts[SGL_NUM_STAGES],
                                 int32_t reset);
 
-/* Release the plan and its device memory (waits for its stream). */
+/* Release the plan and its device memory (waits for its stream).  Ends the
+ * lifetime that sgl_plan began: the point transform, bins, tables and
+ * workspace of the precomputation of Section 6 (Thm. 6.2: everything that
+ * does not depend on fhat or y).  NULL is SGL_E_INVAL. */
 sgl_status sgl_destroy(sgl_plan_t plan);
 
 /* Name and description of the last HIP error this thread's calls turned into
  * SGL_E_DEVICE or SGL_E_NOMEM (empty if none); valid until the next such error. */
 const char *sgl_last_error(void);
 
-/* Static description of a status code. */
+/* Static description of a status code (not a passage of the paper: the
+ * codes are this library's error model; unknown codes give "unknown status"). */
 const char *sgl_status_string(sgl_status s);
 
 #ifdef __cplusplus

@@ -189,22 +189,22 @@ sgl_status setup_geometry(Plan &p) {
   }
   if ((uint64_t)p.ntiles * p.L[0] * p.L[1] * p.L[2] >= (1ull << 32)) return SGL_E_UNSUPPORTED;
   p.mfma = (p.prec == SGL_F32 && p.gather_mode == 0 && p.q <= 8 && p.L[0] == 8 && p.L[1] == 8 && p.L[2] == 8);
-  // scatter blocks over stored cells
-  // 16^3 cells (FP32) or 16 x 16 x 8 (FP64): 32 KB of LDS accumulators
-  const int lo_edge[3] = {16, 16, p.prec == SGL_F64 ? 8 : 16};
+  // blocks of 16^3 stored cells of the cell-owned scatter (the last block of
+  // a dimension may be partial)
   p.nblocks = 1;
   for (int j = 0; j < 3; ++j) {
-    p.Lo[j] = std::min(lo_edge[j], p.E[j]);
+    p.Lo[j] = 16;
     p.To[j] = (p.E[j] + p.Lo[j] - 1) / p.Lo[j];
     p.nblocks *= p.To[j];
   }
   // worst-case number of bin rows a block visits must fit the kernel's table
+  // (768 slots: bins in dimensions 0 and 1 times at most 3 dimension-2 intervals)
   int64_t rows = 3;
   for (int j = 0; j < 2; ++j) {
     const int span = p.Lo[j] + 2 * p.q - 1;
     rows *= std::min<int64_t>(p.T[j], span / p.L[j] + 2 + (p.pruned[j] ? 0 : 2));
   }
-  if (rows > 512) return SGL_E_UNSUPPORTED;
+  if (rows > 768) return SGL_E_UNSUPPORTED;
   // FFT passes: [outer][axis][inner] views; every pass computes in FP64.  The
   // forward runs dimension 1 (n1 -> E1 rows), 0 (n0 -> E0) and last 2, the one
   // that doubles (n2 -> N2), so both intermediates stay near the size of eta;

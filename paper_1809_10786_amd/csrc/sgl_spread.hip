@@ -20,10 +20,11 @@
 //    box to a staging slot of its own; a fold pass then sums, for every stored
 //    cell, the boxes that cover it in a fixed order.  No atomics of any kind:
 //    every grid cell is written by exactly one workgroup.
-//  * scatter (direct): output-driven, for grids whose window box does not fit
-//    in LDS; each workgroup owns a block of stored cells, accumulates in LDS
-//    the contributions of every point whose taps reach the block, and writes
-//    the block once.
+//  * scatter (cell-owned): output-driven, for any cutoff (used where the
+//    window box does not fit in LDS); each workgroup owns a block of stored
+//    cells, every thread a row of that block in registers, and sums the taps
+//    of every point whose window reaches the block in a fixed order; the
+//    block is written once.
 //  * FP32 plans with tiles of 8^3 cells use the matrix-core forms instead
 //    (k_gather_mfma, k_spread_mfma): the dimension-2 contraction of the gather
 //    and the contraction over the points of the scatter run as FP16 hi/lo
@@ -488,7 +489,13 @@ __global__ __launch_bounds__(256) void k_gather_direct(const cplx<R> *__restrict
 //   d theta / d x = (x z, y z, -rxy^2) / (r^2 rxy),   d phi / d x = (-y, x, 0) / rxy^2.
 // Output: grad_ic = Re(conj(g_i) d f_i / d x_ic), the gradient of a real loss
 // whose gradient with respect to f is g (conjugate Wirtinger convention).
-// Undefined (NaN) on the z axis, at the origin and at r >= rho.
+// At r = rho (x~_0 = 0, the outermost point of a plan whose rho is max r) the
+// factor d x~_0 / d r is unbounded while d f / d x~_0 vanishes: f depends on
+// x~_0 only through cos x~_0 = (2r - rho)/rho, so with F(cos t) = f(t),
+// d f / d r = (2/rho) F'(1) = -(2/rho) d^2 f / d x~_0^2 at t = 0.  That limit
+// is taken for rho - r <= 1e-14 rho (t <= 2e-7, where its O((2B t)^2)
+// relative error is below 1e-9).  Undefined (NaN) on the z axis, at the
+// origin and at r > rho.
 template <class R, int Q2>
 __global__ __launch_bounds__(256) void k_grad_points(const cplx<R> *__restrict__ grid,
                                                      const PointRec<R> *__restrict__ pts,
@@ -512,10 +519,12 @@ __global__ __launch_bounds__(256) void k_grad_points(const cplx<R> *__restrict__
     i2[t] = stored_index(b2 - q + 1 + t, 2, g);
   }
   cplx<R> f0 = {0, 0}, f1 = {0, 0}, f2 = {0, 0};  // d f / d u_0, u_1, u_2
+  cplx<R> f00 = {0, 0};                             // d^2 f / d u_0^2
   for (int t0 = 0; t0 < Q2; ++t0) {
     const int s0 = stored_index(b0 - q + 1 + t0, 0, g);
     const R e0 = pr.frac[0] + (R)(q - 1 - t0);
     const R w0 = gauss<R>(e0, inv2lam), dw0 = -e0 * invlam * w0;
+    const R ddw0 = (e0 * e0 * invlam - (R)1) * invlam * w0;
     cplx<R> a = {0, 0}, a1 = {0, 0}, a2 = {0, 0};
     for (int t1 = 0; t1 < Q2; ++t1) {
       const int s1 = stored_index(b1 - q + 1 + t1, 1, g);
@@ -540,6 +549,8 @@ __global__ __launch_bounds__(256) void k_grad_points(const cplx<R> *__restrict__
     }
     f0.re += dw0 * a.re;
     f0.im += dw0 * a.im;
+    f00.re += ddw0 * a.re;
+    f00.im += ddw0 * a.im;
     f1.re += w0 * a1.re;
     f1.im += w0 * a1.im;
     f2.re += w0 * a2.re;
@@ -555,12 +566,20 @@ __global__ __launch_bounds__(256) void k_grad_points(const cplx<R> *__restrict__
   const double c1 = ((double)gv.re * f1.re + (double)gv.im * f1.im) * g.N[1] * inv2pi;
   const double c2 = ((double)gv.re * f2.re + (double)gv.im * f2.im) * g.N[2] * inv2pi;
   double gx = NAN, gy = NAN, gz = NAN;
-  if (rxy > 0.0 && r < rho) {
-    const double dt0 = -1.0 / (r * sqrt(r * (rho - r)));  // d x~_0 / d r divided by r
+  if (rxy > 0.0 && r <= rho) {
+    // Re(conj(g) d f / d r): the chain rule through d x~_0 / d r = -1 / sqrt(r (rho - r)),
+    // or its limit at x~_0 = 0
+    double drad;
+    if (rho - r > 1e-14 * rho) {
+      drad = -c0 / sqrt(r * (rho - r));
+    } else {
+      const double s0 = g.N[0] * inv2pi;
+      drad = -2.0 / rho * ((double)gv.re * f00.re + (double)gv.im * f00.im) * s0 * s0;
+    }
     const double r2 = r * r, rxy2 = rxy * rxy;
-    gx = c0 * dt0 * x + c1 * x * z / (r2 * rxy) - c2 * y / rxy2;
-    gy = c0 * dt0 * y + c1 * y * z / (r2 * rxy) + c2 * x / rxy2;
-    gz = c0 * dt0 * z - c1 * rxy / r2;
+    gx = drad * x / r + c1 * x * z / (r2 * rxy) - c2 * y / rxy2;
+    gy = drad * y / r + c1 * y * z / (r2 * rxy) + c2 * x / rxy2;
+    gz = drad * z / r - c1 * rxy / r2;
   }
   grad[3 * (size_t)i] = (R)gx;
   grad[3 * (size_t)i + 1] = (R)gy;
@@ -569,42 +588,6 @@ __global__ __launch_bounds__(256) void k_grad_points(const cplx<R> *__restrict__
 
 // ---------------------------------------------------------------- scatter
 
-// Taps t in [0, Q2) of a point with base cell b whose stored index falls in
-// the block [S, S + ext): at most two runs t in [tb, te) with block offset
-// ub + (t - tb).
-__device__ inline int tap_runs(int b, int S, int ext, int j, const Geom &g, int Q2, int *tb, int *te, int *ub) {
-  const int q = Q2 / 2;
-  if (g.pruned[j]) {
-    // stored index of tap t is b + t
-    const int lo = max(0, S - b), hi = min(Q2, S + ext - b);
-    if (lo >= hi) return 0;
-    tb[0] = lo;
-    te[0] = hi;
-    ub[0] = b + lo - S;
-    return 1;
-  }
-  const int N = g.N[j];
-  int d = (b - q + 1 - S) % N;  // block offset of tap 0, mod N
-  if (d < 0) d += N;
-  int n = 0;
-  const int a_hi = min(min(Q2, N - d), ext - d);
-  if (a_hi > 0) {
-    tb[n] = 0;
-    te[n] = a_hi;
-    ub[n] = d;
-    ++n;
-  }
-  const int b_lo = N - d, b_hi = min(Q2, ext + N - d);
-  if (b_lo < b_hi) {
-    tb[n] = b_lo;
-    te[n] = b_hi;
-    ub[n] = 0;
-    ++n;
-  }
-  return n;
-}
-
-constexpr int kMaxRows = 512;
 
 // Bins (tiles of base cells) in dimension j whose points can touch stored
 // cells [S, S + ext): merged disjoint bin intervals [first, last].
@@ -652,111 +635,153 @@ __device__ inline int bin_ranges(int S, int ext, int j, const Geom &g, int *firs
   return n;
 }
 
+// ---------------------------------------------------------------- scatter, cell-owned
+
+// Output-driven spreading without atomics, for any cutoff q: workgroup b owns
+// a block of kOwn^3 stored cells and sums into registers the taps of every
+// point whose window reaches the block.  Thread (u0, u1) owns the block's row
+// of kOwn cells along dimension 2, so each cell has exactly one writer and its
+// sum runs over the points in a fixed order (the candidate bins in index
+// order, the points of a bin in their sorted order): the result is
+// deterministic and the block is written once.
+// Per batch of kOwnBatch points the workgroup stages in LDS, for every point,
+// its window restricted to the block along each dimension (kOwn values per
+// dimension, zero outside the 2q taps) and its sample; a thread then adds
+// (y w0[u0] w1[u1]) w2[c] to its kOwn cells when its row lies in the point's
+// footprint.  A wave owns four consecutive u0 rows, so a point whose window
+// misses them costs the wave only the footprint test.
+constexpr int kOwn = 16;
+constexpr int kOwnThreads = kOwn * kOwn;
+constexpr int kOwnBatch = 64;
+constexpr int kOwnMaxRows = 3 * 256;
+
 template <class R, int Q2>
-__global__ __launch_bounds__(256) void k_scatter(const cplx<R> *__restrict__ y, const PointRec<R> *__restrict__ pts,
-                                                 const int32_t *__restrict__ perm,
-                                                 const int32_t *__restrict__ tile_start, Geom g, R inv2lam,
-                                                 cplx<R> *__restrict__ grid) {
-  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  R *acc = (R *)smem;
-  __shared__ int row_start[kMaxRows];
-  __shared__ int row_pref[kMaxRows + 1];
-  __shared__ int nrows_s;
+__global__ __launch_bounds__(kOwnThreads) void k_scatter_owned(const cplx<R> *__restrict__ y,
+                                                               const PointRec<R> *__restrict__ pts,
+                                                               const int32_t *__restrict__ perm,
+                                                               const int32_t *__restrict__ tile_start, Geom g,
+                                                               R inv2lam, cplx<R> *__restrict__ grid) {
   constexpr int q = Q2 / 2;
+  __shared__ R sw[3][kOwnBatch][kOwn];
+  __shared__ cplx<R> sy[kOwnBatch];
+  __shared__ R sfrac[3][kOwnBatch];
+  __shared__ int sbase[3][kOwnBatch];
+  __shared__ int row_start[kOwnMaxRows];
+  __shared__ int row_pref[kOwnMaxRows + 1];
+  __shared__ int rng_f[3][3], rng_l[3][3], rng_n[3];
   const int C2 = blockIdx.x % g.To[2];
   const int C1 = (blockIdx.x / g.To[2]) % g.To[1];
   const int C0 = blockIdx.x / (g.To[2] * g.To[1]);
-  const int S0 = C0 * g.Lo[0], S1 = C1 * g.Lo[1], S2 = C2 * g.Lo[2];
-  const int ext0 = min(g.Lo[0], g.E[0] - S0), ext1 = min(g.Lo[1], g.E[1] - S1), ext2 = min(g.Lo[2], g.E[2] - S2);
-  const int ncell = g.Lo[0] * g.Lo[1] * g.Lo[2];
-  for (int e = threadIdx.x; e < 2 * ncell; e += blockDim.x) acc[e] = 0;
-  if (threadIdx.x == 0) {
-    int f0[3], l0[3], f1[3], l1[3], f2[3], l2[3];
-    const int n0 = bin_ranges(S0, ext0, 0, g, f0, l0);
-    const int n1 = bin_ranges(S1, ext1, 1, g, f1, l1);
-    const int n2 = bin_ranges(S2, ext2, 2, g, f2, l2);
-    int nr = 0, tot = 0;
-    for (int a = 0; a < n0; ++a)
-      for (int x0 = f0[a]; x0 <= l0[a]; ++x0)
-        for (int b = 0; b < n1; ++b)
-          for (int x1 = f1[b]; x1 <= l1[b]; ++x1)
-            for (int c = 0; c < n2; ++c) {
-              const int t0 = (x0 * g.T[1] + x1) * g.T[2];
-              const int s = tile_start[t0 + f2[c]], e = tile_start[t0 + l2[c] + 1];
-              if (e > s && nr < kMaxRows) {
-                row_start[nr] = s;
-                row_pref[nr] = tot;
-                tot += e - s;
-                ++nr;
-              }
-            }
-    row_pref[nr] = tot;
-    nrows_s = nr;
+  const int S[3] = {C0 * kOwn, C1 * kOwn, C2 * kOwn};
+  const int ext0 = min(kOwn, g.E[0] - S[0]), ext1 = min(kOwn, g.E[1] - S[1]), ext2 = min(kOwn, g.E[2] - S[2]);
+  // candidate bins per dimension: merged intervals [first, last]
+  if (threadIdx.x < 3) {
+    const int j = threadIdx.x;
+    const int ext = j == 0 ? ext0 : (j == 1 ? ext1 : ext2);
+    rng_n[j] = bin_ranges(S[j], ext, j, g, rng_f[j], rng_l[j]);
   }
   __syncthreads();
-  const int nr = nrows_s;
-  const int total = row_pref[nr];
-  for (int gidx = threadIdx.x; gidx < total; gidx += blockDim.x) {
-    int lo = 0, hi = nr - 1;
-    while (lo < hi) {  // last row with row_pref <= gidx
-      const int mid = (lo + hi + 1) / 2;
-      if (row_pref[mid] <= gidx) lo = mid; else hi = mid - 1;
+  // one bin row (x0, x1, a dimension-2 interval) per slot: its point range
+  int nr0 = 0, nr1 = 0;
+  for (int a = 0; a < rng_n[0]; ++a) nr0 += rng_l[0][a] - rng_f[0][a] + 1;
+  for (int a = 0; a < rng_n[1]; ++a) nr1 += rng_l[1][a] - rng_f[1][a] + 1;
+  const int n2r = rng_n[2];
+  const int nslots = nr0 * nr1 * n2r;  // at most kOwnMaxRows (checked when the plan is made)
+  for (int sidx = threadIdx.x; sidx < nslots; sidx += kOwnThreads) {
+    const int c = sidx % n2r, pr = sidx / n2r;
+    int i0 = pr / nr1, i1 = pr % nr1, x0 = 0, x1 = 0;
+    for (int a = 0; a < rng_n[0]; ++a) {
+      const int n = rng_l[0][a] - rng_f[0][a] + 1;
+      if (i0 < n) { x0 = rng_f[0][a] + i0; break; }
+      i0 -= n;
     }
-    const int k = row_start[lo] + (gidx - row_pref[lo]);
-    const PointRec<R> pr = pts[k];
-    const int b0 = cell0(pr.cell), b1 = cell1(pr.cell), b2 = cell2(pr.cell);
-    int tb0[2], te0[2], ub0[2], tb1[2], te1[2], ub1[2], tb2[2], te2[2], ub2[2];
-    const int r0 = tap_runs(b0, S0, ext0, 0, g, Q2, tb0, te0, ub0);
-    if (!r0) continue;
-    const int r1 = tap_runs(b1, S1, ext1, 1, g, Q2, tb1, te1, ub1);
-    if (!r1) continue;
-    const int r2 = tap_runs(b2, S2, ext2, 2, g, Q2, tb2, te2, ub2);
-    if (!r2) continue;
-    const cplx<R> yv = y[perm[k]];
-    // Gaussian weights along a run by the recurrence w(t+1) = w(t) r(t),
-    // r(t+1) = r(t) c, with r(t) = exp((2 d_t - 1) / (2 lambda)), c = exp(-1/lambda),
-    // d_t = frac + q - 1 - t; carried in double.
-    const double il = (double)inv2lam;
-    const double cc = exp(-2.0 * il);
-    for (int i0 = 0; i0 < r0; ++i0) {
-      double d0 = (double)pr.frac[0] + (q - 1 - tb0[i0]);
-      double w0 = exp(-d0 * d0 * il), q0 = exp((2.0 * d0 - 1.0) * il);
-      for (int t0 = tb0[i0]; t0 < te0[i0]; ++t0) {
-        const int u0 = ub0[i0] + t0 - tb0[i0];
-        for (int i1 = 0; i1 < r1; ++i1) {
-          double d1 = (double)pr.frac[1] + (q - 1 - tb1[i1]);
-          double w1 = exp(-d1 * d1 * il), q1 = exp((2.0 * d1 - 1.0) * il);
-          for (int t1 = tb1[i1]; t1 < te1[i1]; ++t1) {
-            const int u1 = ub1[i1] + t1 - tb1[i1];
-            const double w01 = w0 * w1;
-            const R yr = (R)(yv.re * w01), yi = (R)(yv.im * w01);
-            R *rowacc = acc + 2 * ((u0 * g.Lo[1] + u1) * g.Lo[2]);
-            for (int i2 = 0; i2 < r2; ++i2) {
-              const double d2 = (double)pr.frac[2] + (q - 1 - tb2[i2]);
-              double w2 = exp(-d2 * d2 * il), q2 = exp((2.0 * d2 - 1.0) * il);
-              int u2 = ub2[i2];
-              for (int t2 = tb2[i2]; t2 < te2[i2]; ++t2, ++u2) {
-                const R wr = (R)w2;
-                atomicAdd(rowacc + 2 * u2, yr * wr);
-                atomicAdd(rowacc + 2 * u2 + 1, yi * wr);
-                w2 *= q2;
-                q2 *= cc;
-              }
-            }
-            w1 *= q1;
-            q1 *= cc;
-          }
+    for (int a = 0; a < rng_n[1]; ++a) {
+      const int n = rng_l[1][a] - rng_f[1][a] + 1;
+      if (i1 < n) { x1 = rng_f[1][a] + i1; break; }
+      i1 -= n;
+    }
+    const int t0 = (x0 * g.T[1] + x1) * g.T[2];
+    const int st = tile_start[t0 + rng_f[2][c]], en = tile_start[t0 + rng_l[2][c] + 1];
+    row_start[sidx] = st;
+    row_pref[sidx] = en - st;  // count, turned into a prefix sum below
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int tot = 0;
+    for (int r = 0; r < nslots; ++r) {
+      const int n = row_pref[r];
+      row_pref[r] = tot;
+      tot += n;
+    }
+    row_pref[nslots] = tot;
+  }
+  __syncthreads();
+  const int total = row_pref[nslots];
+  const int u0 = threadIdx.x / kOwn, u1 = threadIdx.x % kOwn;
+  R are[kOwn], aim[kOwn];
+#pragma unroll
+  for (int c = 0; c < kOwn; ++c) are[c] = aim[c] = 0;
+  for (int b0 = 0; b0 < total; b0 += kOwnBatch) {
+    const int nb = min(kOwnBatch, total - b0);
+    // 1. the batch's point records and samples
+    if ((int)threadIdx.x < nb) {
+      const int gidx = b0 + threadIdx.x;
+      int lo = 0, hi = nslots - 1;
+      while (lo < hi) {  // last slot with row_pref <= gidx
+        const int mid = (lo + hi + 1) / 2;
+        if (row_pref[mid] <= gidx) lo = mid; else hi = mid - 1;
+      }
+      const int k = row_start[lo] + (gidx - row_pref[lo]);
+      const PointRec<R> pr = pts[k];
+      sfrac[0][threadIdx.x] = pr.frac[0];
+      sfrac[1][threadIdx.x] = pr.frac[1];
+      sfrac[2][threadIdx.x] = pr.frac[2];
+      sbase[0][threadIdx.x] = cell0(pr.cell);
+      sbase[1][threadIdx.x] = cell1(pr.cell);
+      sbase[2][threadIdx.x] = cell2(pr.cell);
+      sy[threadIdx.x] = y[perm[k]];
+    }
+    __syncthreads();
+    // 2. each point's window on the block, per dimension: tap t of cell u
+    //    (stored index S + u) or zero
+    for (int e = threadIdx.x; e < 3 * kOwnBatch * kOwn; e += kOwnThreads) {
+      const int u = e % kOwn, pp = (e / kOwn) % kOwnBatch, j = e / (kOwn * kOwnBatch);
+      R w = 0;
+      if (pp < nb) {
+        const int s = S[j] + u;
+        int t;
+        if (g.pruned[j]) {
+          t = s + g.lo[j] - sbase[j][pp] + q - 1;
+        } else {
+          t = (s - (sbase[j][pp] - q + 1)) % g.N[j];
+          if (t < 0) t += g.N[j];
         }
-        w0 *= q0;
-        q0 *= cc;
+        if (t >= 0 && t < Q2) w = gauss<R>(sfrac[j][pp] + (R)(q - 1 - t), inv2lam);
+      }
+      sw[j][pp][u] = w;
+    }
+    __syncthreads();
+    // 3. taps into the thread's row, points in order
+    for (int pp = 0; pp < nb; ++pp) {
+      const R w01 = sw[0][pp][u0] * sw[1][pp][u1];
+      if (w01 != (R)0) {
+        const cplx<R> yv = sy[pp];
+        const R cr = yv.re * w01, ci = yv.im * w01;
+#pragma unroll
+        for (int c = 0; c < kOwn; ++c) {
+          const R w = sw[2][pp][c];
+          are[c] += cr * w;
+          aim[c] += ci * w;
+        }
       }
     }
+    __syncthreads();
   }
-  __syncthreads();
-  for (int e = threadIdx.x; e < ext0 * ext1 * ext2; e += blockDim.x) {
-    const int u2 = e % ext2, r = e / ext2, u1 = r % ext1, u0 = r / ext1;
-    const int c = (u0 * g.Lo[1] + u1) * g.Lo[2] + u2;
-    grid[((size_t)(S0 + u0) * g.E[1] + (S1 + u1)) * g.E[2] + (S2 + u2)] = cplx<R>{acc[2 * c], acc[2 * c + 1]};
+  if (u0 < ext0 && u1 < ext1) {
+    cplx<R> *row = grid + ((size_t)(S[0] + u0) * g.E[1] + (S[1] + u1)) * g.E[2] + S[2];
+#pragma unroll
+    for (int c = 0; c < kOwn; ++c)
+      if (c < ext2) row[c] = cplx<R>{are[c], aim[c]};
   }
 }
 
@@ -802,22 +827,24 @@ __global__ __launch_bounds__(512) void k_spread_rows(const cplx<R> *__restrict__
   for (int i = 0; i < X2; ++i) are[i] = aim[i] = 0;
   for (int b0 = 0; b0 < count; b0 += kSpreadBatch) {
     const int nb = min(kSpreadBatch, count - b0);
-    if ((int)threadIdx.x < nb) {
-      const int k = start + b0 + threadIdx.x;
+    // the workgroup may have fewer threads than a batch has points (boxes of
+    // fewer than kSpreadBatch rows): stage with a stride
+    for (int e = threadIdx.x; e < nb; e += blockDim.x) {
+      const int k = start + b0 + e;
       const PointRec<R> pr = pts[k];
       const int o0 = cell0(pr.cell) - c0 * g.L[0];
       const int o1 = cell1(pr.cell) - c1 * g.L[1];
       const int o2 = cell2(pr.cell) - c2 * g.L[2];
-      so[threadIdx.x] = o0 | (o1 << 8);
-      sy[threadIdx.x] = y[perm[k]];
+      so[e] = o0 | (o1 << 8);
+      sy[e] = y[perm[k]];
 #pragma unroll
       for (int t = 0; t < Q2; ++t) {
-        sw0[threadIdx.x][t] = gauss<R>(pr.frac[0] + (R)(q - 1 - t), inv2lam);
-        sw1[threadIdx.x][t] = gauss<R>(pr.frac[1] + (R)(q - 1 - t), inv2lam);
+        sw0[e][t] = gauss<R>(pr.frac[0] + (R)(q - 1 - t), inv2lam);
+        sw1[e][t] = gauss<R>(pr.frac[1] + (R)(q - 1 - t), inv2lam);
       }
       for (int c = 0; c < X2P; ++c) {
         const int t = c - o2;
-        sw2[threadIdx.x][c] = (t >= 0 && t < Q2) ? gauss<R>(pr.frac[2] + (R)(q - 1 - t), inv2lam) : (R)0;
+        sw2[e][c] = (t >= 0 && t < Q2) ? gauss<R>(pr.frac[2] + (R)(q - 1 - t), inv2lam) : (R)0;
       }
     }
     __syncthreads();
@@ -1319,9 +1346,8 @@ hipError_t scatter_q(const Plan &p, const void *f, void *grid) {
       return hipErrorInvalidValue;
     }
   }
-  const size_t lds = 2 * (size_t)p.Lo[0] * p.Lo[1] * p.Lo[2] * sizeof(R);
-  k_scatter<R, Q2><<<(unsigned)p.nblocks, 256, lds, p.stream>>>((const cplx<R> *)f, (const PointRec<R> *)p.pts,
-                                                                p.perm, p.tile_start, g, inv2lam, (cplx<R> *)grid);
+  k_scatter_owned<R, Q2><<<(unsigned)p.nblocks, kOwnThreads, 0, p.stream>>>(
+      (const cplx<R> *)f, (const PointRec<R> *)p.pts, p.perm, p.tile_start, g, inv2lam, (cplx<R> *)grid);
   return hipGetLastError();
 }
 

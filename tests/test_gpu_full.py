@@ -2,10 +2,16 @@
 
 * the throughput workload (B=64, M=4e6, FP32 and FP64) in the launch
   configuration the benchmark times, the B=32, M=1e6 mixed point set and the
-  B=48, M=2e6 anisotropic mixture: forward outputs at sampled points against
-  the direct sum (Def. 1.3), the adjoint on samples supported on a subset of
-  the points against the direct adjoint, and the adjoint identity
-  <Lambda fhat, y> = <fhat, Lambda^H y> with every point;
+  B=48, M=2e6 anisotropic mixture, against the direct sum (Def. 1.3):
+  - the forward element by element on 2^16 seeded sampled points;
+  - the adjoint of DENSE samples (all M points, iid complex N(0, 1)) element
+    by element against the direct adjoint Lambda^H y (every one of the Nc
+    coefficients), which exercises every chunk, the running exponent of the
+    FP32 spread, and the full-size fold;
+  - two adjoint runs on the same input equal bit for bit (no atomics, fixed
+    summation order);
+  - the adjoint identity <Lambda fhat, y> = <fhat, Lambda^H y> with every
+    point;
 * the FP32 NFFT stage (matrix-core gather and spread, tiles of 8^3 cells)
   against the FP64 stepwise Gaussian NFFT: several tiles with ragged point
   counts, one tile holding more than one chunk of points, all-zero input and
@@ -59,48 +65,57 @@ def check_workload(name, prec, seed, nsample, tol, idtol):
     import paper_1809_10786_amd as sgl
 
     w, pts, fh, y = wl.workload(name, seed=seed)
-    B = w["B"]
-    say(f"full {name} {prec} B={B} M={len(pts)} q={w['q']}")
+    B, M = w["B"], len(pts)
+    say(f"full {name} {prec} B={B} M={M} q={w['q']}")
     rdt, cdt = (torch.float64, torch.complex128) if prec == "f64" else (torch.float32, torch.complex64)
     p = sgl.Plan(dev(pts, rdt), B, sigma=w["sigma"], q=w["q"], precision=prec)
     if prec == "f32":
         assert p.info()["gather_mode"] == 2  # the matrix-core gather and spread
-    pu, fhu = as_used(pts, prec), as_used(fh, prec)
+    pu, fhu, yu = as_used(pts, prec), as_used(fh, prec), as_used(y, prec)
     f = host(p.forward(dev(fh, cdt)))
-    idx = np.sort(np.random.default_rng(seed + 7).choice(len(pts), nsample, replace=False))
+    idx = np.sort(np.random.default_rng(seed + 7).choice(M, min(nsample, M), replace=False))
     f0 = oracle.direct_forward(B, pu[idx], fhu)
-    say(f"  forward rel l2 {rel(f[idx], f0):.3g} max {relinf(f[idx], f0):.3g}")
+    say(f"  forward ({len(idx)} points) rel l2 {rel(f[idx], f0):.3g} max {relinf(f[idx], f0):.3g}")
     assert rel(f[idx], f0) < tol and relinf(f[idx], f0) < tol
-    ys = np.zeros(len(pts), dtype=np.complex128)
-    ys[idx] = y[idx]
-    g = host(p.adjoint(dev(ys, cdt)))
-    g0 = oracle.direct_adjoint(B, pu[idx], as_used(ys, prec)[idx])
+    # dense adjoint: every point carries a sample
+    dy = dev(y, cdt)
+    g = host(p.adjoint(dy))
+    g2 = host(p.adjoint(dy))
+    assert np.array_equal(g, g2), "two adjoint runs differ"
+    say(f"  adjoint of dense y: direct sum over {M} points ...")
+    g0 = oracle.direct_adjoint(B, pu, yu)
     say(f"  adjoint rel l2 {rel(g, g0):.3g} max {relinf(g, g0):.3g}")
     assert rel(g, g0) < tol and relinf(g, g0) < tol
     # adjoint identity with every point
-    g = host(p.adjoint(dev(y, cdt)))
-    yu = as_used(y, prec)
     lhs, rhs = np.vdot(yu, f), np.vdot(g, fhu)
     say(f"  identity {abs(lhs - rhs) / (np.linalg.norm(yu) * np.linalg.norm(f)):.3g}")
     assert abs(lhs - rhs) < idtol * np.linalg.norm(yu) * np.linalg.norm(f)
     p.close()
 
 
+NFWD = 1 << 16
+
+
 def test_b64_m4e6_f32_launch_configuration():
-    check_workload("b64_m4e6_f32", "f32", 11, 400, 1e-5, 2e-6)
+    check_workload("b64_m4e6_f32", "f32", 11, NFWD, 1e-5, 2e-6)
 
 
 def test_b64_m4e6_f64():
-    check_workload("b64_m4e6_f64", "f64", 12, 400, 2e-6, 1e-12)
+    check_workload("b64_m4e6_f64", "f64", 12, NFWD, 2e-6, 1e-12)
+
+
+def test_b64_m4e6_f64_q14():
+    """The high-accuracy cutoff q = 14 (cell-owned scatter, direct gather)."""
+    check_workload("b64_m4e6_f64_q14", "f64", 17, NFWD, 1e-10, 1e-12)
 
 
 @pytest.mark.parametrize("prec,tol,idtol", [("f32", 1e-5, 2e-6), ("f64", 2e-6, 1e-12)])
 def test_b32_m1e6_mixed(prec, tol, idtol):
-    check_workload("b32_m1e6_" + prec, prec, 13, 1500, tol, idtol)
+    check_workload("b32_m1e6_" + prec, prec, 13, NFWD, tol, idtol)
 
 
 def test_b48_m2e6_anisotropic_mixture_f32():
-    check_workload("b48_m2e6_f32", "f32", 14, 800, 1e-5, 2e-6)
+    check_workload("b48_m2e6_f32", "f32", 14, NFWD, 1e-5, 2e-6)
 
 
 # ------------------------------------------------------------ FP32 NFFT stage

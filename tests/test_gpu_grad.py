@@ -145,3 +145,33 @@ def test_grad_points_differentiation_workload_shape():
     assert np.all(np.isfinite(gr[idx]))
     assert err(gr[idx], g0) < 1e-4
     p.close()
+
+
+@pytest.mark.parametrize("B,prec,q,tol", [(12, "f64", 10, 1e-7), (12, "f32", 6, 1e-4)])
+def test_grad_points_default_rho_outermost_point(B, prec, q, tol):
+    """A plan with the default rho = max |x| (eq. nfsglft_rho) puts the outermost
+    point at x~_0 = 0, where the radial chain rule takes its limit through the
+    second window derivative: every gradient is finite, and the outermost
+    point's own gradient matches the oracle's analytic one."""
+    import paper_1809_10786_amd as sgl
+
+    pts = wl.gaussian_points(800, 120 + B)
+    rdt, cdt = (torch.float64, torch.complex128) if prec == "f64" else (torch.float32, torch.complex64)
+    pu = pts.astype(np.float32).astype(np.float64) if prec == "f32" else pts
+    fh = wl.coefficients(B, 121 + B)
+    g = wl.samples(len(pts), 122 + B)
+    if prec == "f32":
+        fh = fh.astype(np.complex64).astype(np.complex128)
+        g = g.astype(np.complex64).astype(np.complex128)
+    P = dev(pu, rdt)
+    p = sgl.Plan(P, B, q=q, precision=prec)
+    k = int(np.argmax(np.linalg.norm(pu, axis=1)))
+    assert abs(p.rho - np.linalg.norm(pu[k])) <= 1e-14 * p.rho
+    gr = host(p.grad_points(dev(fh, cdt), P, dev(g, cdt))).astype(np.float64)
+    assert np.all(np.isfinite(gr))
+    g0 = oracle_grad(B, pu, fh, g)
+    ek = float(np.abs(gr[k] - g0[k]).max() / np.abs(g0[k]).max())
+    say(f"grad default rho B={B} {prec}: all points {err(gr, g0):.3g}, outermost point {ek:.3g}")
+    assert err(gr, g0) < tol
+    assert ek < 10 * tol
+    p.close()

@@ -93,6 +93,8 @@ WORKLOADS = {
     # Throughput workload: B=64, M=4e6 Gaussian points, n^-1.5, FP32, q=6.
     "b64_m4e6_f32": dict(B=64, M=4_000_000, points="gaussian", decay=1.5, sigma=2, q=6, prec="f32"),
     "b64_m4e6_f64": dict(B=64, M=4_000_000, points="gaussian", decay=1.5, sigma=2, q=6, prec="f64"),
+    # The same at the high-accuracy cutoff q = 14 (Theorem 2.7; ~1e-10 and below in FP64).
+    "b64_m4e6_f64_q14": dict(B=64, M=4_000_000, points="gaussian", decay=1.5, sigma=2, q=14, prec="f64"),
     # Inverse transform: B=32, M=3e5 FP64 points in eight clusters (Dirichlet(1) weights), n^-1.5, q=6.
     "b32_m3e5_clustered_f64": dict(B=32, M=300_000, points="clustered8", decay=1.5, sigma=2, q=6, prec="f64"),
     # B=48, M=2e6 FP32 points from a 3-component anisotropic Gaussian mixture, n^-1.5, q=6.
