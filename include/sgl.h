@@ -209,6 +209,22 @@ sgl_status sgl_mlp_forward(sgl_plan_t plan, const float *params_dev, const float
  * deterministic (fixed-order reduction).  Synchronous. */
 sgl_status sgl_mlp_backward(sgl_plan_t plan, const float *params_dev, const float *feat_dev, const float *dc_dev,
                             float *grad_dev);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * sgl_mlp_backward with its per-block partial gradients (128 points a block)
+ * kept in a fixed device array of the library instead of a per-call
+ * allocation.  The array holds SGL_MLP_NOALLOC_MAX_POINTS / 128 blocks of
+ * sgl_mlp_num_params floats (46.5 MB on every device the call runs on, held
+ * until the process ends).  Same result as sgl_mlp_backward, bit for bit.
+ * Allocates nothing, does not synchronise: enqueued on the plan's stream.
+ * The first call on a device looks up the array's address on that device.
+ * SGL_E_UNSUPPORTED for plans with more than SGL_MLP_NOALLOC_MAX_POINTS
+ * points; SGL_E_INVAL for null arguments.  Every call on one device shares
+ * the array: calls that overlap in time on one device (two streams, two host
+ * threads) race and return wrong gradients. */
+#define SGL_MLP_NOALLOC_MAX_POINTS 327680
+sgl_status sgl_mlp_backward_noalloc(sgl_plan_t plan, const float *params_dev, const float *feat_dev,
+                                    const float *dc_dev, float *grad_dev);
 /* One Adam step (Kingma & Ba) on the parameters; m_dev, v_dev: moment buffers
  * (start at zero), step >= 1. */
 sgl_status sgl_mlp_adam(sgl_plan_t plan, float *params_dev, const float *grad_dev, float *m_dev, float *v_dev,

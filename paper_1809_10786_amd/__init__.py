@@ -25,7 +25,9 @@ SYMBOLS = (
     "sgl_last_error", "sgl_grad_points", "sgl_cgnr", "sgl_mlp_num_params", "sgl_point_features",
     "sgl_mlp_forward", "sgl_mlp_backward", "sgl_mlp_adam", "sgl_mlp_weights", "sgl_mlp_weight_grad",
     "sgl_mlp_train_step", "sgl_batch_create", "sgl_batch_run", "sgl_batch_destroy", "sgl_forward_adjoint",
+    "sgl_mlp_backward_noalloc",
 )
+SGL_MLP_NOALLOC_MAX_POINTS = 327680
 
 STAGES = ("conv_radial", "conv_polar", "fft_A", "fft_B", "fft_C", "gather", "scatter", "fft_Ch", "fft_Bh",
           "fft_Ah", "conv_polar_adj", "conv_radial_adj", "ndft", "ndft_adj", "fold")
@@ -85,6 +87,7 @@ def lib():
         L.sgl_mlp_num_params.argtypes, L.sgl_mlp_num_params.restype = [], i32
         for name, args in (("sgl_point_features", [vp, vp, vp]), ("sgl_mlp_forward", [vp, vp, vp, vp]),
                            ("sgl_mlp_backward", [vp, vp, vp, vp, vp]),
+                           ("sgl_mlp_backward_noalloc", [vp, vp, vp, vp, vp]),
                            ("sgl_mlp_adam", [vp, vp, vp, vp, vp, f32, f32, f32, f32, i32]),
                            ("sgl_mlp_weights", [vp, vp, vp, vp]), ("sgl_mlp_weight_grad", [vp, vp, vp, vp, f64, vp]),
                            ("sgl_mlp_train_step", [vp, vp, vp, vp, vp, vp, i32, f32, i32, ctypes.POINTER(f64)])):

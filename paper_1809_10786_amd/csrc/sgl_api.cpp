@@ -700,6 +700,14 @@ sgl_status sgl_mlp_backward(sgl_plan_t plan, const float *params_dev, const floa
   return from_hip(launch_mlp_backward(params_dev, feat_dev, dc_dev, plan->p.M, grad_dev, plan->p.stream));
 }
 
+sgl_status sgl_mlp_backward_noalloc(sgl_plan_t plan, const float *params_dev, const float *feat_dev,
+                                    const float *dc_dev, float *grad_dev) {
+  if (check_plan(plan) != SGL_OK || !params_dev || !feat_dev || !dc_dev || !grad_dev) return SGL_E_INVAL;
+  if (plan->p.M > SGL_MLP_NOALLOC_MAX_POINTS) return SGL_E_UNSUPPORTED;
+  return from_hip(launch_mlp_backward_noalloc(params_dev, feat_dev, dc_dev, plan->p.M, grad_dev, plan->p.stream,
+                                              plan->p.device));
+}
+
 sgl_status sgl_mlp_adam(sgl_plan_t plan, float *params_dev, const float *grad_dev, float *m_dev, float *v_dev,
                         float lr, float beta1, float beta2, float eps, int32_t step) {
   if (check_plan(plan) != SGL_OK || !params_dev || !grad_dev || !m_dev || !v_dev || step < 1 || !(lr > 0.0f) ||

@@ -161,6 +161,8 @@ hipError_t launch_point_features(const Plan &p, const void *xyz, float *feat);
 hipError_t launch_mlp_forward(const float *params, const float *feat, int64_t M, float *c, hipStream_t s);
 hipError_t launch_mlp_backward(const float *params, const float *feat, const float *dc, int64_t M, float *grad,
                                hipStream_t s);
+hipError_t launch_mlp_backward_noalloc(const float *params, const float *feat, const float *dc, int64_t M,
+                                       float *grad, hipStream_t s, int device);
 hipError_t launch_adam(float *params, const float *grad, float *m, float *v, int n, float lr, float b1, float b2,
                        float eps, int step, hipStream_t s);
 hipError_t launch_mlp_weights(const Plan &p, const float *c, const float *feat, void *w);

@@ -16,6 +16,7 @@
 //  - Adam update; weights from c; dL/dc from dL/dw.
 // Parameters (float32): W1[64][4], b1[64], W2[64][64], b2[64], W3[64], b3.
 #include <cmath>
+#include <mutex>
 
 #include "sgl_internal.h"
 
@@ -279,6 +280,57 @@ hipError_t launch_mlp_backward(const float *params, const float *feat, const flo
   hipStreamSynchronize(s);
   hipFree(partial);
   return e;
+}
+
+// ---- backward without allocation (sgl_mlp_backward_noalloc)
+// The per-block partial gradients live in this file-scope device array instead
+// of a per-call allocation: kNoAllocBlocks blocks of kBP points, i.e. at most
+// SGL_MLP_NOALLOC_MAX_POINTS points (46.5 MB per device, held until the
+// process ends).  Each device holds its own copy at its own address; host code
+// never passes the array's name (a host-side stand-in) to a kernel, only the
+// address hipGetSymbolAddress returned for that device.
+constexpr int kNoAllocBlocks = SGL_MLP_NOALLOC_MAX_POINTS / kBP;
+static_assert(kNoAllocBlocks * kBP == SGL_MLP_NOALLOC_MAX_POINTS, "whole blocks");
+static __device__ __align__(256) float scratch[(size_t)kNoAllocBlocks * kNParams];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static float *g_scratch[kMaxDevices] = {};
+
+// The device address of `scratch` on `device`, looked up once per device with
+// that device current.
+static hipError_t scratch_on(int device, float **out) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[device]) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != device) {
+      const hipError_t e2 = hipSetDevice(cur);
+      if (e == hipSuccess) e = e2;
+    }
+    if (e != hipSuccess) return e;
+    g_scratch[device] = (float *)ptr;
+  }
+  *out = g_scratch[device];
+  return hipSuccess;
+}
+
+hipError_t launch_mlp_backward_noalloc(const float *params, const float *feat, const float *dc, int64_t M,
+                                       float *grad, hipStream_t s, int device) {
+  float *partial = nullptr;
+  const hipError_t e = scratch_on(device, &partial);
+  if (e != hipSuccess) return e;
+  // the same kernels and summation order as launch_mlp_backward; every
+  // partial the reduction reads is written first, so nothing is cleared
+  const int nblocks = (int)((M + kBP - 1) / kBP);
+  k_mlp_backward<<<nblocks, kBP, 0, s>>>(params, feat, dc, M, partial);
+  k_reduce_partials<<<nb(kNParams), 256, 0, s>>>(partial, nblocks, grad);
+  return hipGetLastError();
 }
 
 hipError_t launch_adam(float *params, const float *grad, float *m, float *v, int n, float lr, float b1, float b2,
