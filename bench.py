@@ -27,6 +27,7 @@ METRIC = "scattered points/s fwd+adj at B=64, M=4e6, rel err≤1e-5; frac of HBM
 # MI355X published peaks
 HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_F16_TFLOPS = 2500.0  # dense FP16 matrix cores
+MFMA_PEAK_F64_TFLOPS = 78.6    # dense FP64 matrix cores
 # FP32 vector FMA issue rate without packed math: 256 CU x 4 SIMD x 16 lanes x
 # 2 flop x 2.4 GHz (the build disables packed FP32 instructions).
 ALU_PEAK_F32_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
@@ -39,7 +40,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="b64_m4e6_f64")
-    ap.add_argument("--beside", nargs="*", default=["b64_m4e6_f32"],
+    ap.add_argument("--beside", nargs="*", default=["b64_m4e6_f32", "b64_m4e6_f64_q14"],
                     help="further workloads measured in the same run and reported beside the headline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--grad", action="store_true",
@@ -143,7 +144,9 @@ def accuracy(B, plan, pts_used, fh_used, f_gpu, y, prec, m, torch, cdt):
 # ---------------------------------------------------------------- profiles
 
 STAGE_KERNEL_VALU = {"gather": "k_gather_tiled", "scatter": "k_spread_rows", "fold": "k_fold_staging"}
+STAGE_KERNEL_DIRECT = {"gather": "k_gather_direct", "scatter": "k_scatter_owned"}
 STAGE_KERNEL_MFMA = {"gather": "k_gather_mfma", "scatter": "k_spread_mfma", "fold": "k_fold_tiles8"}
+STAGE_KERNEL_MFMA64 = {"gather": "k_gather_tiled", "scatter": "k_spread_mfma64", "fold": "k_fold_tiles8"}
 KERNEL_SOURCE = {"k_gather_tiled": "sgl_spread.hip", "k_spread_rows": "sgl_spread.hip",
                  "k_fold_staging": "sgl_spread.hip", "k_gather_mfma": "sgl_spread.hip",
                  "k_spread_mfma": "sgl_spread.hip", "k_fold_tiles8": "sgl_spread.hip", "k_fft": "sgl_fft.hip"}
@@ -151,7 +154,8 @@ KERNEL_SOURCE = {"k_gather_tiled": "sgl_spread.hip", "k_spread_rows": "sgl_sprea
 
 def stage_kernels(info):
     """Kernel that runs each gather/scatter/fold stage of a plan (plan info)."""
-    k = dict(STAGE_KERNEL_MFMA if info["gather_mode"] == 2 else STAGE_KERNEL_VALU)
+    k = dict({1: STAGE_KERNEL_DIRECT, 2: STAGE_KERNEL_MFMA, 3: STAGE_KERNEL_MFMA64}.get(info["gather_mode"],
+                                                                                     STAGE_KERNEL_VALU))
     if (info["L0"], info["L1"], info["L2"]) != (8, 8, 8):
         k["fold"] = "k_fold_staging"
     return k
@@ -217,7 +221,8 @@ def summarize_profiles(kt_dir, fetch_dir, write_dir, out_md, workload):
                      f"{'' if rd is None else f'{rd / 1e6:.1f}'} | {'' if wr is None else f'{wr / 1e6:.1f}'} | "
                      f"{'' if gbs is None else f'{gbs:.0f}'} |")
     lines += ["", "Machine-readable (bytes per launch, with the digest of the kernel's source file):", ""]
-    for k in list(STAGE_KERNEL_MFMA.values()) + list(STAGE_KERNEL_VALU.values()):
+    for k in sorted(set(STAGE_KERNEL_MFMA.values()) | set(STAGE_KERNEL_VALU.values()) |
+                    set(STAGE_KERNEL_MFMA64.values()) | set(STAGE_KERNEL_DIRECT.values())):
         rd = counters["FETCH_SIZE"][1].get(k)
         wr = counters["WRITE_SIZE"][1].get(k)
         if rd is not None and wr is not None:
@@ -289,60 +294,100 @@ def bench_grad(a, torch, wl, sgl):
 
 
 def bench_inverse(a, torch, wl, sgl):
-    """Inverse transform: CGNR to a normal residual of 1e-3 on noisy samples
-    (1 % noise) with W = I, with histogram density weights and with learned
-    weights (network trained on another cloud of the same distribution)."""
-    name = a.workload if a.workload != "b64_m4e6_f64" else "b32_m3e5_clustered_f64"
-    w, pts, fh, _ = wl.workload(name, seed=0)
-    B, M, q, prec = w["B"], w["M"], w["q"], w["prec"]
-    rdt = torch.float64 if prec == "f64" else torch.float32
-    cdt = torch.complex128 if prec == "f64" else torch.complex64
-    Pt = torch.from_numpy(wl.make_points(w["points"], M, 1)).to("cuda", rdt)
-    P = torch.from_numpy(pts).to("cuda", rdt)
-    plan_t = sgl.Plan(Pt, B, sigma=w["sigma"], q=q, precision=prec)
-    net = sgl.WeightNet(seed=4)
-    Ft = net.features(plan_t, Pt)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    steps = 150
-    losses = net.train(plan_t, Ft, steps=steps, nbatch=2, lr=1e-2, decay=w["decay"], seed=5)
-    torch.cuda.synchronize()
-    train_s = time.perf_counter() - t0
-    plan_t.close()
-    print(f"[bench] inverse: trained {steps} steps in {train_s:.2f} s, loss {losses[0]:.4g} -> {losses[-1]:.4g}",
-          file=sys.stderr, flush=True)
-    plan = sgl.Plan(P, B, sigma=w["sigma"], q=q, precision=prec)
-    F = net.features(plan, P)
-    fstar = torch.from_numpy(fh).to("cuda", cdt)
-    y = plan.forward(fstar)
-    rms = torch.sqrt(torch.mean(torch.abs(y) ** 2))
-    g = torch.Generator(device="cuda").manual_seed(7)
-    y = y + torch.complex(torch.randn(M, generator=g, device="cuda", dtype=rdt),
-                          torch.randn(M, generator=g, device="cuda", dtype=rdt)) * (0.01 * rms / 2 ** 0.5)
+    """Inverse transform, CGNR with W = I (plain), histogram density weights and
+    learned weights (network trained with the native step on other clouds of
+    the same distribution), 1 % noise:
+    * the clustered cloud (B=32, M=3e5, eight Gaussian clusters): the clusters
+      leave part of the weighted support unsampled, so the comparison stops at
+      a normal residual of 1e-3;
+    * a cloud covering the ball of radius 5 (B=12, M=2e4, density falling as
+      1/r): iterations and time to a normal residual of 1e-6;
+    and CGNE (the minimum-norm solution, Section 2) for fewer samples than
+    coefficients (B=8, 100 Gaussian points) to a residual of 1e-6."""
+    cases = (("b32_m3e5_clustered_f64", 1e-3, [1], 150, 2, 1e-2),
+             ("b12_m2e4_centered5_f64", 1e-6, [320, 321], 300, 4, 5e-3))
     out = {}
-    for label, wt in (("plain", None), ("histogram", net.weights(plan, F, learned=False)),
-                      ("learned", net.weights(plan, F))):
-        plan.cgnr(y, weights=wt, maxiter=5, tol=1e-3)  # warm-up
+    for name, tol, train_seeds, steps, nbatch, lr in cases:
+        w, pts, fh, _ = wl.workload(name, seed=0)
+        B, M, q, prec = w["B"], w["M"], w["q"], w["prec"]
+        rdt = torch.float64 if prec == "f64" else torch.float32
+        cdt = torch.complex128 if prec == "f64" else torch.complex64
+        net = sgl.WeightNet(seed=4)
+        plans_t, feats_t = [], []
+        for s_ in train_seeds:
+            Pt = torch.from_numpy(wl.make_points(w["points"], M, s_)).to("cuda", rdt)
+            plans_t.append(sgl.Plan(Pt, B, sigma=w["sigma"], q=q, precision=prec))
+            feats_t.append(net.features(plans_t[-1], Pt))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        x, info = plan.cgnr(y, weights=wt, maxiter=5000, tol=1e-3)
+        losses = []
+        per = steps // (len(plans_t) * 3)
+        for r in range(len(plans_t) * 3):
+            k = r % len(plans_t)
+            losses += net.train(plans_t[k], feats_t[k], steps=per, nbatch=nbatch, lr=lr, decay=w["decay"], seed=5 + r)
         torch.cuda.synchronize()
-        s = time.perf_counter() - t0
-        err = float(torch.linalg.vector_norm(x - fstar) / torch.linalg.vector_norm(fstar))
-        out[label] = {"iterations": info["iterations"], "seconds": s,
-                      "ms_per_iteration": s * 1e3 / max(info["iterations"], 1), "rel_error_vs_truth": err,
-                      "rel_normal_residual": info["rel_normal_residual"]}
-        print(f"[bench] inverse {label}: {out[label]}", file=sys.stderr, flush=True)
+        train_s = time.perf_counter() - t0
+        for pt in plans_t:
+            pt.close()
+        print(f"[bench] inverse {name}: trained {len(losses)} steps in {train_s:.2f} s, loss {losses[0]:.4g} -> "
+              f"{losses[-1]:.4g}", file=sys.stderr, flush=True)
+        P = torch.from_numpy(pts).to("cuda", rdt)
+        plan = sgl.Plan(P, B, sigma=w["sigma"], q=q, precision=prec)
+        F = net.features(plan, P)
+        fstar = torch.from_numpy(fh).to("cuda", cdt)
+        y0 = plan.forward(fstar)
+        rms = torch.sqrt(torch.mean(torch.abs(y0) ** 2))
+        g = torch.Generator(device="cuda").manual_seed(7)
+        noisy = y0 + torch.complex(torch.randn(M, generator=g, device="cuda", dtype=rdt),
+                                   torch.randn(M, generator=g, device="cuda", dtype=rdt)) * (0.01 * rms / 2 ** 0.5)
+        res = {"B": B, "M": M, "q": q, "tol": tol, "train_steps": len(losses), "train_seconds": train_s}
+        for data, y in (("noisy", noisy), ("exact", y0)):
+            for label, wt in (("plain", None), ("histogram", net.weights(plan, F, learned=False)),
+                              ("learned", net.weights(plan, F))):
+                plan.cgnr(y, weights=wt, maxiter=5, tol=tol)  # warm-up
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                x, info = plan.cgnr(y, weights=wt, maxiter=20000, tol=tol)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                err = float(torch.linalg.vector_norm(x - fstar) / torch.linalg.vector_norm(fstar))
+                key = label if data == "noisy" else f"{label}_exact_samples"
+                res[key] = {"iterations": info["iterations"], "seconds": dt,
+                            "ms_per_iteration": dt * 1e3 / max(info["iterations"], 1), "rel_error_vs_truth": err,
+                            "rel_normal_residual": info["rel_normal_residual"]}
+                print(f"[bench] inverse {name} {key}: {res[key]}", file=sys.stderr, flush=True)
+        plan.close()
+        out[name] = res
+    # CGNE: fewer samples than coefficients (the under-determined systems of
+    # scattered SGL samples are ill-conditioned: cond(Lambda) is about 4e3 at
+    # B = 8 on 100 Gaussian points and above 1e7 at B = 12 on 400)
+    B, M = 8, 100
+    P = torch.from_numpy(wl.gaussian_points(M, 160)).to("cuda", torch.float64)
+    plan = sgl.Plan(P, B, q=12)
+    fstar = torch.from_numpy(wl.coefficients(B, 161)).to("cuda", torch.complex128)
+    y = plan.forward(fstar)
+    plan.cgne(y, maxiter=5, tol=1e-6)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, info = plan.cgne(y, maxiter=20000, tol=1e-6)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out["cgne_b8_m100_gaussian_f64"] = {"B": B, "M": M, "iterations": info["iterations"], "seconds": dt,
+                                        "rel_residual": info["rel_residual"]}
+    print(f"[bench] cgne {out['cgne_b8_m100_gaussian_f64']}", file=sys.stderr, flush=True)
+    plan.close()
+    cov = out["b12_m2e4_centered5_f64"]
     print(json.dumps({
-        "metric": "CGNR seconds to normal residual 1e-3 (learned weights)", "value": out["learned"]["seconds"],
-        "unit": "s", "n_gpus": 1, "higher_is_better": False, "dtype": prec, "data": "synthetic",
-        "config": {"workload": name, "B": B, "M": M, "q": q, "noise": 0.01, "train_steps": steps,
-                   "train_seconds": train_s}, "solves": out}), flush=True)
+        "metric": "CGNR seconds to normal residual 1e-6 with learned weights (covering cloud)",
+        "value": cov["learned"]["seconds"], "unit": "s", "n_gpus": 1, "higher_is_better": False, "dtype": "f64",
+        "data": "synthetic", "config": {"workload": "b12_m2e4_centered5_f64", "noise": 0.01},
+        "solves": out}), flush=True)
 
 
 def bench_batch(a, torch, wl, sgl):
-    """64 transforms, B uniform over the supported bandwidths in [16, 64], M
-    log-uniform in [1e5, 2e6], mixed points, FP32, coefficients with n^-1 decay:
+    """64 transforms, B uniform in [16, 64] (FFT lengths padded where sigma n has
+    a prime factor above 5), M log-uniform in [1e5, 2e6], mixed points, FP32,
+    coefficients with n^-1 decay:
     forward + adjoint of all of them per step, eagerly (one plan after another
     on one stream) and replayed as one HIP graph over 4 branches."""
     specs = wl.batch_specs(64, seed=0)
@@ -486,6 +531,9 @@ def measure(a, torch, wl, sgl, name, check_points, conv_split16=False, paired=Tr
         if info["gather_mode"] == 2:
             # the contraction runs on the FP16 matrix cores (hi/lo split operands)
             bound, peak = "mfma", MFMA_PEAK_F16_TFLOPS
+        elif info["gather_mode"] == 3:
+            # FP64 matrix cores (published dense FP64 peak)
+            bound, peak = "mfma", MFMA_PEAK_F64_TFLOPS
         else:
             bound, peak = "alu", ALU_PEAK_F32_TFLOPS if prec == "f32" else ALU_PEAK_F64_TFLOPS
         roof = {"kernel": kern[dom], "bound": bound, "achieved": achieved, "peak": peak,

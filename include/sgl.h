@@ -47,7 +47,7 @@ typedef enum {
   SGL_E_RANGE = -2,       /* user rho smaller than max_i |x_i|                      */
   SGL_E_NOMEM = -3,       /* device or host allocation failed                       */
   SGL_E_DEVICE = -4,      /* HIP runtime or launch error                            */
-  SGL_E_UNSUPPORTED = -5  /* e.g. an FFT length with a prime factor above 5         */
+  SGL_E_UNSUPPORTED = -5  /* e.g. a bandwidth whose FFT grid exceeds 2048 x 1024^2  */
 } sgl_status;
 
 typedef enum { SGL_F64 = 0, SGL_F32 = 1 } sgl_precision;
@@ -61,8 +61,11 @@ typedef enum { SGL_F64 = 0, SGL_F32 = 1 } sgl_precision;
  * at plan time, per row; data split per column).  Keeps about 22 bits of every
  * product; the conversion sums cancel strongly when the radial functions grow
  * towards rho, so results are less accurate than the default FP64 products
- * (errors per workload are stated with the design notes). */
+ * (errors per workload are stated with the design notes).  Bandwidths above
+ * SGL_CONV_SPLIT16_MAX_B are refused (SGL_E_UNSUPPORTED, a host-side check):
+ * at B = 64 the adjoint misses 1e-5 relative to the direct sum. */
 #define SGL_FLAG_CONV_SPLIT16 (1u << 1)
+#define SGL_CONV_SPLIT16_MAX_B 48
 
 typedef struct {
   int32_t B;          /* bandwidth, 2 <= B <= 256 (Section 6 assumes B >= 2)              */
@@ -163,6 +166,20 @@ sgl_status sgl_grad_points(sgl_plan_t plan, const void *fhat_dev, const void *po
  * y or w. */
 sgl_status sgl_cgnr(sgl_plan_t plan, const void *y_dev, const void *w_dev, void *fhat_dev, int32_t maxiter,
                     double tol, double *info);
+
+/* Inverse transform for fewer samples than coefficients (M < Nc): the
+ * normal equations of the second kind of Section 2, Lambda Lambda^H g = y with
+ * fhat = Lambda^H g, by CGNE (Golub & Van Loan, Alg. 10.4.2): the
+ * minimum-norm fhat with Lambda fhat = y when the rows of Lambda are
+ * independent and the iteration starts in the range of Lambda^H (e.g. from
+ * zero).  y_dev: M complex samples (caller order); fhat_dev: Nc complex, the
+ * initial guess on entry and the solution on return.  Stops after maxiter
+ * iterations or once |y - Lambda fhat| <= tol |y|.  One forward and one
+ * adjoint transform per iteration; vectors in the plan's precision, scalars in
+ * FP64, reductions in a fixed order.  info (host, 3 doubles, may be NULL):
+ * {iterations, |y - Lambda fhat| / |y|, |fhat|}.  Synchronous.  SGL_E_INVAL
+ * for null y/fhat, negative maxiter or tol, or fhat overlapping y. */
+sgl_status sgl_cgne(sgl_plan_t plan, const void *y_dev, void *fhat_dev, int32_t maxiter, double tol, double *info);
 
 /* ---- Batches of transforms -------------------------------------------------
  * A batch records the forward (fhat_dev[j] -> f_dev[j]) and/or the adjoint
@@ -268,8 +285,9 @@ sgl_status sgl_plan_rho(sgl_plan_t plan, double *rho);
 /* Informational: number of points, FFT grid sigma*n, stored (pruned) grid
  * extents, gather tile edges, and bytes of device workspace.  info must
  * hold 12 int64 values: {M, N0, N1, N2, E0, E1, E2, L0, L1, L2, bytes,
- * gather_mode (0 = LDS tiles, 1 = direct, 2 = LDS tiles with the FP16
- * hi/lo matrix-core gather and spread of FP32 plans)}. */
+ * gather_mode (0 = LDS tiles, 1 = direct gather and cell-owned scatter,
+ * 2 = LDS tiles with the FP16 hi/lo matrix-core gather and spread of FP32
+ * plans, 3 = LDS tiles with the FP64 matrix-core spread of FP64 plans)}. */
 sgl_status sgl_plan_info(sgl_plan_t plan, int64_t info[12]);
 
 /* Stages timed by the optional per-stage profiler (forward: radial and polar

@@ -25,7 +25,7 @@ SYMBOLS = (
     "sgl_last_error", "sgl_grad_points", "sgl_cgnr", "sgl_mlp_num_params", "sgl_point_features",
     "sgl_mlp_forward", "sgl_mlp_backward", "sgl_mlp_adam", "sgl_mlp_weights", "sgl_mlp_weight_grad",
     "sgl_mlp_train_step", "sgl_batch_create", "sgl_batch_run", "sgl_batch_destroy", "sgl_forward_adjoint",
-    "sgl_mlp_backward_noalloc",
+    "sgl_mlp_backward_noalloc", "sgl_cgne",
 )
 SGL_MLP_NOALLOC_MAX_POINTS = 327680
 
@@ -77,6 +77,8 @@ def lib():
         L.sgl_grad_points.argtypes, L.sgl_grad_points.restype = [vp, vp, vp, vp, vp], ctypes.c_int
         L.sgl_forward_adjoint.argtypes, L.sgl_forward_adjoint.restype = [vp, vp, vp, vp, vp], ctypes.c_int
         L.sgl_cgnr.argtypes = [vp, vp, vp, vp, i32, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]
+        L.sgl_cgne.argtypes = [vp, vp, vp, i32, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]
+        L.sgl_cgne.restype = ctypes.c_int
         f32, f64 = ctypes.c_float, ctypes.c_double
         L.sgl_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), i32, ctypes.POINTER(vp),
                                        ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), i32, vp]
@@ -289,6 +291,19 @@ class Plan:
                               ctypes.c_void_p(w.data_ptr()) if w is not None else None,
                               ctypes.c_void_p(x.data_ptr()), int(maxiter), float(tol), info), "sgl_cgnr")
         return x, {"iterations": int(info[0]), "rel_normal_residual": info[1], "weighted_residual_norm": info[2]}
+
+    def cgne(self, y, x0=None, maxiter=100, tol=1e-6):
+        """CGNE for the minimum-norm solution of Lambda fhat = y (fewer samples
+        than coefficients).  Returns (fhat, info) with info = {iterations,
+        rel_residual, norm}; x0 defaults to zero."""
+        yy = self._in(y, self.M, "y")
+        x = self._torch.zeros(self.nc, dtype=self.complex_dtype, device=self.device)
+        if x0 is not None:
+            x.copy_(self._in(x0, self.nc, "x0"))
+        info = (ctypes.c_double * 3)()
+        _check(lib().sgl_cgne(self._h, ctypes.c_void_p(yy.data_ptr()), ctypes.c_void_p(x.data_ptr()), int(maxiter),
+                              float(tol), info), "sgl_cgne")
+        return x, {"iterations": int(info[0]), "rel_residual": info[1], "norm": info[2]}
 
     def close(self):
         if getattr(self, "_h", None):

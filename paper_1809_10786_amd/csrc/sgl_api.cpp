@@ -65,8 +65,9 @@ int lines_per_group(int L, size_t elem) {
 }
 
 void free_plan(Plan &p) {
-  void *bufs[] = {p.pts, p.perm, p.tile_start, p.chunks, p.krad, p.kpol, p.deconv, p.twiddle, p.beta,
-                  p.zeta, p.eta, p.bufX, p.bufY, p.bufZ, p.ptsxyz, p.tile_chunk, p.staging};
+  void *bufs[] = {p.pts,  p.perm, p.tile_start, p.chunks, p.krad,    p.kpol,       p.deconv,   p.twiddle,
+                  p.beta, p.zeta, p.eta,        p.bufX,   p.bufY,    p.bufZ,       p.ptsxyz,   p.tile_chunk,
+                  p.staging, p.own_work, p.own_fold, p.own_stage};
   for (void *b : bufs)
     if (b) hipFree(b);
   free_conv_tables(p);
@@ -146,11 +147,16 @@ sgl_status setup_geometry(Plan &p) {
   p.n[0] = 4 * B;
   p.n[1] = 2 * B;
   p.n[2] = 2 * B;
-  for (int j = 0; j < 3; ++j) p.N[j] = p.sigma * p.n[j];
-  if (p.N[0] > 2048 || p.N[1] > 1024 || p.N[2] > 1024) return SGL_E_UNSUPPORTED;
+  // FFT lengths: sigma n_j when it factors into 2, 3 and 5, else the next even
+  // length that does (the effective oversampling N_j / n_j then exceeds sigma;
+  // the window keeps the lambda of sigma, so its error bound still holds)
   FftPass tmp;
-  for (int j = 0; j < 3; ++j)
-    if (!radices_of(p.N[j], tmp)) return SGL_E_UNSUPPORTED;
+  for (int j = 0; j < 3; ++j) {
+    int N = p.sigma * p.n[j];
+    while (N <= 2048 && !radices_of(N, tmp)) N += 2;
+    p.N[j] = N;
+  }
+  if (p.N[0] > 2048 || p.N[1] > 1024 || p.N[2] > 1024) return SGL_E_UNSUPPORTED;
   p.lambda = p.sigma * (double)p.q / ((2.0 * p.sigma - 1.0) * kPi);
   for (int j = 0; j < 3; ++j) {
     if (j < 2 && p.N[j] / 2 + 2 * p.q < p.N[j]) {
@@ -189,6 +195,8 @@ sgl_status setup_geometry(Plan &p) {
   }
   if ((uint64_t)p.ntiles * p.L[0] * p.L[1] * p.L[2] >= (1ull << 32)) return SGL_E_UNSUPPORTED;
   p.mfma = (p.prec == SGL_F32 && p.gather_mode == 0 && p.q <= 8 && p.L[0] == 8 && p.L[1] == 8 && p.L[2] == 8);
+  p.mfma64 = (p.prec == SGL_F64 && p.gather_mode == 0 && 7 + 2 * p.q <= 24 && p.L[0] == 8 && p.L[1] == 8 &&
+              p.L[2] == 8);
   // blocks of 16^3 stored cells of the cell-owned scatter (the last block of
   // a dimension may be partial)
   p.nblocks = 1;
@@ -312,6 +320,20 @@ sgl_status make_plan(Plan &p, const void *points) {
   SGL_TRY(hipMemcpy(p.tile_chunk, tc.data(), tc.size() * sizeof(int32_t), hipMemcpyHostToDevice));
   if (p.gather_mode == 0)
     SGL_TRY(dev_alloc(p, &p.staging, (size_t)p.nchunks * p.X[0] * p.X[1] * p.X[2] * cbytes(p)));
+  if (p.gather_mode == 1) {
+    // work items of the cell-owned scatter: dense blocks split into segments
+    std::vector<int32_t> work, fold;
+    owned_work_list(p, ts, work, fold, p.nown_slots);
+    p.nown = (int64_t)work.size() / 4;
+    p.nown_fold = (int64_t)fold.size() / 3;
+    SGL_TRY(dev_alloc(p, &p.own_work, work.size() * sizeof(int32_t)));
+    SGL_TRY(hipMemcpy(p.own_work, work.data(), work.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    if (!fold.empty()) {
+      SGL_TRY(dev_alloc(p, &p.own_fold, fold.size() * sizeof(int32_t)));
+      SGL_TRY(hipMemcpy(p.own_fold, fold.data(), fold.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+      SGL_TRY(dev_alloc(p, &p.own_stage, (size_t)p.nown_slots * 16 * 16 * 16 * cbytes(p)));
+    }
+  }
   // 5. tables
   const sgl_status st = p.prec == SGL_F64 ? build_tables<double>(p) : build_tables<float>(p);
   if (st != SGL_OK) return st;
@@ -458,6 +480,7 @@ sgl_status sgl_plan(sgl_plan_t *out, const sgl_params *prm, int64_t M, const voi
   if (prm->flags & ~(uint32_t)(SGL_FLAG_EXACT_NDFT | SGL_FLAG_CONV_SPLIT16)) return SGL_E_INVAL;
   if (!std::isfinite(prm->rho)) return SGL_E_INVAL;
   if (M < 1 || M > 0x7fffffffLL) return SGL_E_INVAL;
+  if ((prm->flags & SGL_FLAG_CONV_SPLIT16) && prm->B > SGL_CONV_SPLIT16_MAX_B) return SGL_E_UNSUPPORTED;
   sgl_plan_s *h = new (std::nothrow) sgl_plan_s;
   if (!h) return SGL_E_NOMEM;
   Plan &p = h->p;
@@ -567,6 +590,15 @@ sgl_status sgl_cgnr(sgl_plan_t plan, const void *y_dev, const void *w_dev, void 
   const size_t nf = sgl_num_coeffs(p.B) * cb, ny = (size_t)p.M * cb, nw = (size_t)p.M * (cb / 2);
   if (overlaps(fhat_dev, nf, y_dev, ny) || (w_dev && overlaps(fhat_dev, nf, w_dev, nw))) return SGL_E_INVAL;
   return cgnr_run(p, y_dev, w_dev, fhat_dev, maxiter, tol, info, plan_forward, plan_adjoint);
+}
+
+sgl_status sgl_cgne(sgl_plan_t plan, const void *y_dev, void *fhat_dev, int32_t maxiter, double tol, double *info) {
+  if (check_plan(plan) != SGL_OK || !y_dev || !fhat_dev || maxiter < 0 || !(tol >= 0.0) || !std::isfinite(tol))
+    return SGL_E_INVAL;
+  Plan &p = plan->p;
+  const size_t cb = cbytes(p);
+  if (overlaps(fhat_dev, sgl_num_coeffs(p.B) * cb, y_dev, (size_t)p.M * cb)) return SGL_E_INVAL;
+  return cgne_run(p, y_dev, fhat_dev, maxiter, tol, info, plan_forward, plan_adjoint);
 }
 
 // ---------------------------------------------------------------- batches
@@ -884,7 +916,7 @@ sgl_status sgl_plan_info(sgl_plan_t plan, int64_t info[12]) {
   if (check_plan(plan) != SGL_OK || !info) return SGL_E_INVAL;
   const Plan &p = plan->p;
   const int64_t v[12] = {p.M, p.N[0], p.N[1], p.N[2], p.E[0], p.E[1], p.E[2],
-                         p.L[0], p.L[1], p.L[2], (int64_t)p.bytes, p.mfma ? 2 : p.gather_mode};
+                         p.L[0], p.L[1], p.L[2], (int64_t)p.bytes, p.mfma ? 2 : (p.mfma64 ? 3 : p.gather_mode)};
   std::memcpy(info, v, sizeof(v));
   return SGL_OK;
 }

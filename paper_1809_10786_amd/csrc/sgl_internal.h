@@ -116,6 +116,7 @@ struct Plan {
   // workgroups of a concurrent scatter
   bool gather_narrow = false;
   int mfma = 0;         // FP32, 8^3 tiles, q <= 8: matrix-core gather and spread
+  int mfma64 = 0;       // FP64, 8^3 tiles, box edge <= 24: FP64 matrix-core spread
   // scatter output blocks over stored cells
   int Lo[3], To[3];
   int64_t nblocks = 0;
@@ -130,6 +131,11 @@ struct Plan {
   int64_t nchunks = 0;
   int32_t *tile_chunk = nullptr;  // ntiles + 1: first chunk of every tile
   void *staging = nullptr;        // nchunks window boxes (tiled scatter)
+  // cell-owned scatter: work items {block, first candidate, count, slot},
+  // folds {block, first slot, slots} and the partial blocks of the slots
+  int32_t *own_work = nullptr, *own_fold = nullptr;
+  int64_t nown = 0, nown_fold = 0, nown_slots = 0;
+  void *own_stage = nullptr;
   int F[3] = {8, 8, 8};           // fold block edges (stored cells)
   void *krad = nullptr, *kpol = nullptr;  // conversion matrices (always FP64)
   ConvTab conv[4];                       // conversion products: FP64 or FP16 hi/lo table operands
@@ -175,6 +181,8 @@ hipError_t launch_norm2(const Plan &p, const void *a, int64_t n, double *out_dev
 sgl_status cgnr_run(Plan &p, const void *y_dev, const void *w_dev, void *fhat_dev, int maxiter, double tol,
                     double *info, sgl_status (*fwd)(Plan &, const void *, void *),
                     sgl_status (*adj)(Plan &, const void *, void *));
+sgl_status cgne_run(Plan &p, const void *y_dev, void *fhat_dev, int maxiter, double tol, double *info,
+                    sgl_status (*fwd)(Plan &, const void *, void *), sgl_status (*adj)(Plan &, const void *, void *));
 hipError_t launch_conv_unfold(const Plan &p, void *eta, int eta_f64);
 hipError_t launch_conv_fold_eta(const Plan &p, const void *eta, int eta_f64);
 sgl_status build_conv_tables(Plan &p, const std::vector<long double> &kr, const std::vector<long double> &kp);
@@ -185,6 +193,9 @@ hipError_t launch_fft_pass(const Plan &p, const FftPass &fp, const void *in, voi
                            int in_f64, int out_f64);
 hipError_t launch_gather(const Plan &p, const void *grid, void *f);
 hipError_t launch_scatter(const Plan &p, const void *f, void *grid);
+// work list of the cell-owned scatter from the host copy of tile_start
+void owned_work_list(const Plan &p, const std::vector<int32_t> &ts, std::vector<int32_t> &work,
+                     std::vector<int32_t> &fold, int64_t &nslots);
 hipError_t launch_fold(const Plan &p, void *grid);  // sums in FP64, writes the grid in the plan's precision
 hipError_t launch_ndft_forward(const Plan &p, const void *eta, void *f);
 hipError_t launch_ndft_adjoint(const Plan &p, const void *f, void *eta);

@@ -197,6 +197,93 @@ done:
   return SGL_OK;
 }
 
+// CGNE (Golub & Van Loan, Alg. 10.4.2; Craig's method) for the normal
+// equations of the second kind of an under-determined system (Section 2):
+// Lambda Lambda^H g = y, fhat = Lambda^H g, the minimum-norm solution when
+// the iteration starts from fhat in the range of Lambda^H (e.g. zero).  In
+// terms of fhat: r = y - Lambda fhat, p = Lambda^H r, then per iteration
+//   alpha = |r|^2 / |p|^2,  fhat += alpha p,  r -= alpha Lambda p,
+//   beta = |r_new|^2 / |r|^2,  p = Lambda^H r + beta p.
+template <class R>
+static sgl_status cgne_typed(Plan &p, const void *y_dev, void *fhat_dev, int maxiter, double tol, double *info,
+                             sgl_status (*fwd)(Plan &, const void *, void *),
+                             sgl_status (*adj)(Plan &, const void *, void *)) {
+  Solver<R> S{p};
+  S.y = (const cplx<R> *)y_dev;
+  S.w = nullptr;
+  S.x = (cplx<R> *)fhat_dev;
+  S.M = p.M;
+  S.nc = (int64_t)p.B * (p.B + 1) * (2 * p.B + 1) / 6;
+  void *ws = nullptr;
+  const size_t cb = sizeof(cplx<R>);
+  const size_t bytes = 2 * (size_t)S.M * cb + 2 * (size_t)S.nc * cb + (kRedBlocks + 1) * sizeof(double);
+  if (hipMalloc(&ws, bytes) != hipSuccess) return SGL_E_NOMEM;
+  char *b = (char *)ws;
+  S.r = (cplx<R> *)b;
+  S.q = S.r + S.M;
+  S.s = S.q + S.M;
+  S.pv = S.s + S.nc;
+  S.t = nullptr;
+  S.partial = (double *)(S.pv + S.nc);
+  S.scalar = S.partial + kRedBlocks;
+  sgl_status st = SGL_OK;
+  hipError_t e = hipSuccess;
+  double yy = 0.0, rr = 0.0, pp = 0.0, xx = 0.0;
+  int it = 0;
+#define CG_TRY_ST(x)             \
+  do {                           \
+    st = (x);                    \
+    if (st != SGL_OK) goto done; \
+  } while (0)
+#define CG_TRY_HIP(x)               \
+  do {                              \
+    e = (x);                        \
+    if (e != hipSuccess) goto done; \
+  } while (0)
+  CG_TRY_HIP(S.dot(S.y, S.y, nullptr, S.M, &yy));
+  // r = y - Lambda x, p = Lambda^H r
+  CG_TRY_ST(fwd(p, S.x, S.q));
+  k_wsub<R><<<blocks(S.M), 256, 0, p.stream>>>(S.r, S.y, S.q, nullptr, S.M);
+  CG_TRY_ST(adj(p, S.r, S.pv));
+  CG_TRY_HIP(S.dot(S.r, S.r, nullptr, S.M, &rr));
+  while (it < maxiter && yy > 0.0 && std::sqrt(rr / yy) > tol) {
+    CG_TRY_HIP(S.dot(S.pv, S.pv, nullptr, S.nc, &pp));            // |p|^2
+    if (!(pp > 0.0)) break;
+    const double alpha = rr / pp;
+    k_axpy<R><<<blocks(S.nc), 256, 0, p.stream>>>(S.x, S.pv, alpha, S.nc);   // x += alpha p
+    CG_TRY_ST(fwd(p, S.pv, S.q));                                   // q = Lambda p
+    k_axpy<R><<<blocks(S.M), 256, 0, p.stream>>>(S.r, S.q, -alpha, S.M);     // r -= alpha q
+    double rnew = 0.0;
+    CG_TRY_HIP(S.dot(S.r, S.r, nullptr, S.M, &rnew));
+    const double beta = rnew / rr;
+    rr = rnew;
+    CG_TRY_ST(adj(p, S.r, S.s));                                    // s = Lambda^H r
+    k_xpby<R><<<blocks(S.nc), 256, 0, p.stream>>>(S.pv, S.s, beta, S.nc);    // p = s + beta p
+    ++it;
+  }
+  CG_TRY_HIP(S.dot(S.x, S.x, nullptr, S.nc, &xx));
+done:
+#undef CG_TRY_ST
+#undef CG_TRY_HIP
+  hipStreamSynchronize(p.stream);
+  hipFree(ws);
+  if (st != SGL_OK) return st;
+  if (e != hipSuccess) return e == hipErrorOutOfMemory ? SGL_E_NOMEM : SGL_E_DEVICE;
+  if (info) {
+    info[0] = it;
+    info[1] = yy > 0.0 ? std::sqrt(rr / yy) : 0.0;  // |r| / |y|
+    info[2] = std::sqrt(xx);                        // |fhat|
+  }
+  return SGL_OK;
+}
+
+sgl_status cgne_run(Plan &p, const void *y_dev, void *fhat_dev, int maxiter, double tol, double *info,
+                    sgl_status (*fwd)(Plan &, const void *, void *),
+                    sgl_status (*adj)(Plan &, const void *, void *)) {
+  return p.prec == SGL_F64 ? cgne_typed<double>(p, y_dev, fhat_dev, maxiter, tol, info, fwd, adj)
+                           : cgne_typed<float>(p, y_dev, fhat_dev, maxiter, tol, info, fwd, adj);
+}
+
 sgl_status cgnr_run(Plan &p, const void *y_dev, const void *w_dev, void *fhat_dev, int maxiter, double tol,
                     double *info, sgl_status (*fwd)(Plan &, const void *, void *),
                     sgl_status (*adj)(Plan &, const void *, void *)) {

@@ -171,6 +171,7 @@ typedef _Float16 sgl_half2 __attribute__((ext_vector_type(2)));
 typedef _Float16 sgl_half4 __attribute__((ext_vector_type(4)));
 typedef float sgl_float4 __attribute__((ext_vector_type(4)));
 typedef float sgl_float2 __attribute__((ext_vector_type(2)));
+typedef double sgl_double4 __attribute__((ext_vector_type(4)));
 
 constexpr int kPlaneK = 24;  // i2 slots an MFMA row reads; K slots 24..31 meet zero weights
 constexpr int kLdsMax = 160 * 1024;
@@ -591,7 +592,7 @@ __global__ __launch_bounds__(256) void k_grad_points(const cplx<R> *__restrict__
 
 // Bins (tiles of base cells) in dimension j whose points can touch stored
 // cells [S, S + ext): merged disjoint bin intervals [first, last].
-__device__ inline int bin_ranges(int S, int ext, int j, const Geom &g, int *first, int *last) {
+__host__ __device__ inline int bin_ranges(int S, int ext, int j, const Geom &g, int *first, int *last) {
   const int q = g.q, L = g.L[j], NB = g.NB[j];
   int cand_lo[3], cand_hi[3], nc = 0;
   if (g.pruned[j]) {
@@ -635,11 +636,199 @@ __device__ inline int bin_ranges(int S, int ext, int j, const Geom &g, int *firs
   return n;
 }
 
+// FP64 matrix-core form of the tiled spreading (FP64 data, tiles of 8^3
+// cells): for the points of one chunk the window box is the product
+//   D[(i0, i1)][(i2, c)] = sum_p (w0_p[i0] w1_p[i1]) (y_p^c w2_p[i2]),
+// c = re, im, on v_mfma_f64_16x16x4f64 with K = 4 points per step: A[row][p]
+// = w0 w1, B[p][col] with the real and imaginary parts interleaved along the
+// columns (col = 2 i2 + c, 2X columns in three blocks of 16 for X <= 24), so
+// every product is an exact FP64 multiply-add.  Per batch of kSB64 points the
+// workgroup stages the w0 and w1 tables and B in LDS; wave w owns the row
+// blocks w, w + 8, ... of the box for the whole chunk (accumulators in
+// registers) and skips, per K step, the row blocks outside
+// [min o0, max o0 + 2q) of its four points (A = 0 there).  The box goes to the
+// chunk's staging slot; the fold sums the boxes.  No atomics.
+constexpr int kSpread64Threads = 1024;  // 16 waves
+constexpr int kSB64 = 64;              // points staged at once
+constexpr int kTW64 = 33;              // doubles per w0/w1 table row (box index, padded)
+constexpr int kBT64 = 50;              // doubles per B row (48 columns, padded)
+
+template <int Q2>
+__global__ __launch_bounds__(kSpread64Threads) void k_spread_mfma64(const cplx<double> *__restrict__ y,
+                                                                    const PointRec<double> *__restrict__ pts,
+                                                                    const int32_t *__restrict__ perm,
+                                                                    const int32_t *__restrict__ chunks, Geom g,
+                                                                    double inv2lam,
+                                                                    cplx<double> *__restrict__ staging) {
+  constexpr int q = Q2 / 2;
+  constexpr int X = 8 + Q2 - 1;  // box edge in every dimension
+  constexpr int nrow = X * X;
+  constexpr int nrb = (nrow + 15) / 16;
+  constexpr int NCB = (2 * X + 15) / 16;
+  constexpr int NW = kSpread64Threads / 64;
+  constexpr int RBW = (nrb + NW - 1) / NW;
+  static_assert(X <= 24 && NCB <= 3, "box edge exceeds three column blocks");
+  static_assert((nrb * 16 - 1) / X < 32, "row index past the weight tables");
+  // tw[d][p][i]: w_d of point p at box index i, d = 0, 1; zero outside the
+  // point's window, in particular for i >= X (rows past the box) and for the
+  // invalid points of a partial batch
+  __shared__ double tw[2][kSB64][kTW64];
+  __shared__ double bt[kSB64][kBT64];     // B[p][col], zero past 2X
+  __shared__ double sfr[3][kSB64];
+  __shared__ int so[3][kSB64];
+  __shared__ cplx<double> sy[kSB64];
+  __shared__ int srb[kSB64 / 4][2];       // row blocks a K step of 4 points meets
+
+  const int tidx = chunks[3 * blockIdx.x];
+  const int start = chunks[3 * blockIdx.x + 1];
+  const int count = chunks[3 * blockIdx.x + 2];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int pl = lane & 15, kq = lane >> 4;
+  const int c0 = tidx / (g.T[2] * g.T[1]), c1 = (tidx / g.T[2]) % g.T[1], c2 = tidx % g.T[2];
+
+  sgl_double4 acc[RBW][NCB];
+#pragma unroll
+  for (int r = 0; r < RBW; ++r)
+#pragma unroll
+    for (int n = 0; n < NCB; ++n) acc[r][n] = sgl_double4{0.0, 0.0, 0.0, 0.0};
+
+  // the next batch's point data, one value per thread (threads 0 .. 6 kSB64 - 1:
+  // field f = t / kSB64 of point t % kSB64: fractions 0..2, base cell, sample
+  // re, im), loaded while the current batch is multiplied
+  const int pf = threadIdx.x % kSB64, ff = threadIdx.x / kSB64;
+  double nv = 0.0;
+  int ncell = 0;
+  auto fetch = [&](int b0n) {
+    if (ff < 6 && b0n + pf < count) {
+      const int k = start + b0n + pf;
+      if (ff < 3) {
+        nv = pts[k].frac[ff];
+      } else if (ff == 3) {
+        ncell = pts[k].cell;
+      } else {
+        const cplx<double> v = y[perm[k]];
+        nv = ff == 4 ? v.re : v.im;
+      }
+    }
+  };
+  fetch(0);
+
+  for (int b0 = 0; b0 < count; b0 += kSB64) {
+    const int nb = min(kSB64, count - b0);
+    // 1. the batch's point records and samples (fetched during the last batch)
+    if (ff < 6) {
+      const bool valid = pf < nb;
+      if (ff < 3) {
+        sfr[ff][pf] = valid ? nv : 0.0;
+      } else if (ff == 3) {
+        // offsets in [0, 8): the point lies in this tile; far outside every box when invalid
+        so[0][pf] = valid ? cell0(ncell) - c0 * 8 : 1 << 20;
+        so[1][pf] = valid ? cell1(ncell) - c1 * 8 : 1 << 20;
+        so[2][pf] = valid ? cell2(ncell) - c2 * 8 : 1 << 20;
+      } else if (ff == 4) {
+        sy[pf].re = valid ? nv : 0.0;
+      } else {
+        sy[pf].im = valid ? nv : 0.0;
+      }
+    }
+    __syncthreads();
+    // 2. zero tables, then per point and dimension its 2q window values by the
+    //    Gaussian recurrence: with d_t = frac + q - 1 - t, w_{t+1} = w_t r_t,
+    //    r_t = exp((2 d_t - 1) / (2 lambda)), r_{t+1} = r_t exp(-1 / lambda)
+    //    (dimensions 0 and 1 into the weight tables, dimension 2 times the
+    //    sample into B)
+    for (int e = threadIdx.x; e < 2 * kSB64 * kTW64; e += kSpread64Threads) (&tw[0][0][0])[e] = 0.0;
+    for (int e = threadIdx.x; e < kSB64 * kBT64; e += kSpread64Threads) (&bt[0][0])[e] = 0.0;
+    __syncthreads();
+    if ((int)threadIdx.x < 3 * kSB64) {
+      const int d = threadIdx.x / kSB64, pp = threadIdx.x % kSB64;
+      if (pp < nb) {
+        const double cc = exp(-2.0 * inv2lam);
+        const double d0 = sfr[d][pp] + (double)(q - 1);
+        double w = exp(-d0 * d0 * inv2lam), r = exp((2.0 * d0 - 1.0) * inv2lam);
+        const int o = so[d][pp];
+        const cplx<double> yv = sy[pp];
+        for (int t = 0; t < Q2; ++t) {
+          if (d < 2) {
+            tw[d][pp][o + t] = w;
+          } else {
+            bt[pp][2 * (o + t)] = yv.re * w;
+            bt[pp][2 * (o + t) + 1] = yv.im * w;
+          }
+          w *= r;
+          r *= cc;
+        }
+      }
+    }
+    if ((int)threadIdx.x < kSB64 / 4) {
+      // rows i0 * X + i1 with i0 outside [min o0, max o0 + Q2) of a K step's
+      // points have A = 0 there: the step only needs the row blocks between
+      const int k4 = threadIdx.x;
+      int lo = X, hi = 0;
+      for (int j = 0; j < 4; ++j) {
+        const int pp = 4 * k4 + j;
+        if (pp < nb) {
+          lo = min(lo, so[0][pp]);
+          hi = max(hi, so[0][pp]);
+        }
+      }
+      srb[k4][0] = lo < X ? (lo * X) / 16 : nrb;
+      srb[k4][1] = lo < X ? min(nrb, ((hi + Q2) * X + 15) / 16) : nrb;
+    }
+    __syncthreads();
+    if (b0 + kSB64 < count) fetch(b0 + kSB64);
+    // 3. products over the batch, K = 4 points per step
+    for (int ks = 0; ks < nb; ks += 4) {
+      const int kr_lo = srb[ks / 4][0], kr_hi = srb[ks / 4][1];
+      const int pp = ks + kq;  // this lane's point of the K step (A column, B row)
+      double bf[NCB];
+#pragma unroll
+      for (int n = 0; n < NCB; ++n) bf[n] = bt[pp][16 * n + pl];
+#pragma unroll
+      for (int r = 0; r < RBW; ++r) {
+        const int rb = wave + r * NW;
+        if (rb < nrb && rb >= kr_lo && rb < kr_hi) {
+          const int row = rb * 16 + pl;
+          const int i0 = row / X, i1 = row - (row / X) * X;
+          const double a = tw[0][pp][i0] * tw[1][pp][i1];
+#pragma unroll
+          for (int n = 0; n < NCB; ++n) acc[r][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bf[n], acc[r][n], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();  // the batch's tables are consumed
+  }
+  // D[kq + 4v][pl] of every (row block, column block) to the chunk's box
+  double *out = (double *)(staging + (size_t)blockIdx.x * nrow * X);
+#pragma unroll
+  for (int r = 0; r < RBW; ++r) {
+    const int rb = wave + r * NW;
+    if (rb < nrb) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = rb * 16 + kq + 4 * v;
+        if (row < nrow) {
+#pragma unroll
+          for (int n = 0; n < NCB; ++n) {
+            const int col = 16 * n + pl;  // 2 i2 + c
+            if (col < 2 * X) out[(size_t)row * 2 * X + col] = acc[r][n][v];
+          }
+        }
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------- scatter, cell-owned
 
-// Output-driven spreading without atomics, for any cutoff q: workgroup b owns
-// a block of kOwn^3 stored cells and sums into registers the taps of every
-// point whose window reaches the block.  Thread (u0, u1) owns the block's row
+// Output-driven spreading without atomics, for any cutoff q: a workgroup owns
+// a block of kOwn^3 stored cells and sums into registers the taps of the
+// points whose windows reach the block.  The candidate points of a block (the
+// points of the bins that can reach it, in bin order) are split at plan time
+// into segments of at most kOwnSeg points, one work item each, so dense
+// blocks do not serialise the launch: a block with one segment is written to
+// the grid directly, the segments of a denser block write partial blocks to
+// slots of their own that k_fold_owned sums in segment order.  Thread (u0, u1) owns the block's row
 // of kOwn cells along dimension 2, so each cell has exactly one writer and its
 // sum runs over the points in a fixed order (the candidate bins in index
 // order, the points of a bin in their sorted order): the result is
@@ -652,6 +841,7 @@ __device__ inline int bin_ranges(int S, int ext, int j, const Geom &g, int *firs
 // misses them costs the wave only the footprint test.
 constexpr int kOwn = 16;
 constexpr int kOwnThreads = kOwn * kOwn;
+constexpr int kOwnSeg = 8192;  // candidate points per work item
 constexpr int kOwnBatch = 64;
 constexpr int kOwnMaxRows = 3 * 256;
 
@@ -659,8 +849,10 @@ template <class R, int Q2>
 __global__ __launch_bounds__(kOwnThreads) void k_scatter_owned(const cplx<R> *__restrict__ y,
                                                                const PointRec<R> *__restrict__ pts,
                                                                const int32_t *__restrict__ perm,
-                                                               const int32_t *__restrict__ tile_start, Geom g,
-                                                               R inv2lam, cplx<R> *__restrict__ grid) {
+                                                               const int32_t *__restrict__ tile_start,
+                                                               const int32_t *__restrict__ work, Geom g,
+                                                               R inv2lam, cplx<R> *__restrict__ grid,
+                                                               cplx<R> *__restrict__ stage) {
   constexpr int q = Q2 / 2;
   __shared__ R sw[3][kOwnBatch][kOwn];
   __shared__ cplx<R> sy[kOwnBatch];
@@ -669,9 +861,12 @@ __global__ __launch_bounds__(kOwnThreads) void k_scatter_owned(const cplx<R> *__
   __shared__ int row_start[kOwnMaxRows];
   __shared__ int row_pref[kOwnMaxRows + 1];
   __shared__ int rng_f[3][3], rng_l[3][3], rng_n[3];
-  const int C2 = blockIdx.x % g.To[2];
-  const int C1 = (blockIdx.x / g.To[2]) % g.To[1];
-  const int C0 = blockIdx.x / (g.To[2] * g.To[1]);
+  // work item: block, first candidate, candidate count (-1: to the end), slot (-1: the grid)
+  const int blk = work[4 * blockIdx.x], seg0 = work[4 * blockIdx.x + 1];
+  const int segn = work[4 * blockIdx.x + 2], slot = work[4 * blockIdx.x + 3];
+  const int C2 = blk % g.To[2];
+  const int C1 = (blk / g.To[2]) % g.To[1];
+  const int C0 = blk / (g.To[2] * g.To[1]);
   const int S[3] = {C0 * kOwn, C1 * kOwn, C2 * kOwn};
   const int ext0 = min(kOwn, g.E[0] - S[0]), ext1 = min(kOwn, g.E[1] - S[1]), ext2 = min(kOwn, g.E[2] - S[2]);
   // candidate bins per dimension: merged intervals [first, last]
@@ -717,12 +912,13 @@ __global__ __launch_bounds__(kOwnThreads) void k_scatter_owned(const cplx<R> *__
   }
   __syncthreads();
   const int total = row_pref[nslots];
+  const int first = min(seg0, total), end = segn < 0 ? total : min(total, seg0 + segn);
   const int u0 = threadIdx.x / kOwn, u1 = threadIdx.x % kOwn;
   R are[kOwn], aim[kOwn];
 #pragma unroll
   for (int c = 0; c < kOwn; ++c) are[c] = aim[c] = 0;
-  for (int b0 = 0; b0 < total; b0 += kOwnBatch) {
-    const int nb = min(kOwnBatch, total - b0);
+  for (int b0 = first; b0 < end; b0 += kOwnBatch) {
+    const int nb = min(kOwnBatch, end - b0);
     // 1. the batch's point records and samples
     if ((int)threadIdx.x < nb) {
       const int gidx = b0 + threadIdx.x;
@@ -777,11 +973,49 @@ __global__ __launch_bounds__(kOwnThreads) void k_scatter_owned(const cplx<R> *__
     }
     __syncthreads();
   }
-  if (u0 < ext0 && u1 < ext1) {
+  if (slot >= 0) {
+    cplx<R> *row = stage + ((size_t)slot * kOwnThreads + threadIdx.x) * kOwn;
+#pragma unroll
+    for (int c = 0; c < kOwn; ++c) row[c] = cplx<R>{are[c], aim[c]};
+  } else if (u0 < ext0 && u1 < ext1) {
     cplx<R> *row = grid + ((size_t)(S[0] + u0) * g.E[1] + (S[1] + u1)) * g.E[2] + S[2];
 #pragma unroll
     for (int c = 0; c < kOwn; ++c)
       if (c < ext2) row[c] = cplx<R>{are[c], aim[c]};
+  }
+}
+
+// Sum of the partial blocks of the blocks with more than one work item, in
+// segment order (FP64 sums, written in the plan's precision): fold entry b is
+// {block, first slot, number of slots}.
+template <class R>
+__global__ __launch_bounds__(kOwnThreads) void k_fold_owned(const cplx<R> *__restrict__ stage,
+                                                            const int32_t *__restrict__ fold, Geom g,
+                                                            cplx<R> *__restrict__ grid) {
+  const int blk = fold[3 * blockIdx.x], s0 = fold[3 * blockIdx.x + 1], ns = fold[3 * blockIdx.x + 2];
+  const int C2 = blk % g.To[2];
+  const int C1 = (blk / g.To[2]) % g.To[1];
+  const int C0 = blk / (g.To[2] * g.To[1]);
+  const int S0 = C0 * kOwn, S1 = C1 * kOwn, S2 = C2 * kOwn;
+  const int ext0 = min(kOwn, g.E[0] - S0), ext1 = min(kOwn, g.E[1] - S1), ext2 = min(kOwn, g.E[2] - S2);
+  const int u0 = threadIdx.x / kOwn, u1 = threadIdx.x % kOwn;
+  double ar[kOwn], ai[kOwn];
+#pragma unroll
+  for (int c = 0; c < kOwn; ++c) ar[c] = ai[c] = 0.0;
+  for (int k = 0; k < ns; ++k) {
+    const cplx<R> *row = stage + ((size_t)(s0 + k) * kOwnThreads + threadIdx.x) * kOwn;
+#pragma unroll
+    for (int c = 0; c < kOwn; ++c) {
+      const cplx<R> v = row[c];
+      ar[c] += v.re;
+      ai[c] += v.im;
+    }
+  }
+  if (u0 < ext0 && u1 < ext1) {
+    cplx<R> *row = grid + ((size_t)(S0 + u0) * g.E[1] + (S1 + u1)) * g.E[2] + S2;
+#pragma unroll
+    for (int c = 0; c < kOwn; ++c)
+      if (c < ext2) row[c] = cplx<R>{(R)ar[c], (R)ai[c]};
   }
 }
 
@@ -1332,6 +1566,14 @@ hipError_t scatter_q(const Plan &p, const void *f, void *grid) {
       return hipGetLastError();
     }
   }
+  if constexpr (std::is_same<R, double>::value && Q2 <= 16) {
+    if (p.mfma64) {
+      k_spread_mfma64<Q2><<<(unsigned)p.nchunks, kSpread64Threads, 0, p.stream>>>(
+          (const cplx<double> *)f, (const PointRec<double> *)p.pts, p.perm, p.chunks, g, (double)inv2lam,
+          (cplx<double> *)p.staging);
+      return hipGetLastError();
+    }
+  }
   if (p.gather_mode == 0) {
     if constexpr (Q2 <= 16) {
       const unsigned threads = (unsigned)((p.X[0] * p.X[1] + 63) / 64 * 64);
@@ -1346,8 +1588,12 @@ hipError_t scatter_q(const Plan &p, const void *f, void *grid) {
       return hipErrorInvalidValue;
     }
   }
-  k_scatter_owned<R, Q2><<<(unsigned)p.nblocks, kOwnThreads, 0, p.stream>>>(
-      (const cplx<R> *)f, (const PointRec<R> *)p.pts, p.perm, p.tile_start, g, inv2lam, (cplx<R> *)grid);
+  k_scatter_owned<R, Q2><<<(unsigned)p.nown, kOwnThreads, 0, p.stream>>>(
+      (const cplx<R> *)f, (const PointRec<R> *)p.pts, p.perm, p.tile_start, p.own_work, g, inv2lam,
+      (cplx<R> *)grid, (cplx<R> *)p.own_stage);
+  if (p.nown_fold > 0)
+    k_fold_owned<R><<<(unsigned)p.nown_fold, kOwnThreads, 0, p.stream>>>((const cplx<R> *)p.own_stage, p.own_fold,
+                                                                         g, (cplx<R> *)grid);
   return hipGetLastError();
 }
 
@@ -1472,6 +1718,43 @@ hipError_t fold_r(const Plan &p, void *grid) {
   }
 
 }  // namespace
+
+void owned_work_list(const Plan &p, const std::vector<int32_t> &ts, std::vector<int32_t> &work,
+                     std::vector<int32_t> &fold, int64_t &nslots) {
+  const Geom g = make_geom(p);
+  work.clear();
+  fold.clear();
+  nslots = 0;
+  for (int64_t b = 0; b < p.nblocks; ++b) {
+    const int C2 = (int)(b % p.To[2]), C1 = (int)((b / p.To[2]) % p.To[1]), C0 = (int)(b / ((int64_t)p.To[2] * p.To[1]));
+    const int S[3] = {C0 * kOwn, C1 * kOwn, C2 * kOwn};
+    int f[3][3], l[3][3], n[3];
+    for (int j = 0; j < 3; ++j) n[j] = bin_ranges(S[j], std::min(kOwn, p.E[j] - S[j]), j, g, f[j], l[j]);
+    // candidate points: the kernel's slot order (x0, x1, dimension-2 interval)
+    int64_t tot = 0;
+    for (int a = 0; a < n[0]; ++a)
+      for (int x0 = f[0][a]; x0 <= l[0][a]; ++x0)
+        for (int c = 0; c < n[1]; ++c)
+          for (int x1 = f[1][c]; x1 <= l[1][c]; ++x1)
+            for (int e = 0; e < n[2]; ++e) {
+              const int64_t t0 = ((int64_t)x0 * p.T[1] + x1) * p.T[2];
+              tot += ts[t0 + l[2][e] + 1] - ts[t0 + f[2][e]];
+            }
+    const int nseg = (int)std::max<int64_t>(1, (tot + kOwnSeg - 1) / kOwnSeg);
+    if (nseg > 1) {
+      fold.push_back((int32_t)b);
+      fold.push_back((int32_t)nslots);
+      fold.push_back(nseg);
+    }
+    for (int k = 0; k < nseg; ++k) {
+      work.push_back((int32_t)b);
+      work.push_back(k * kOwnSeg);
+      work.push_back(k + 1 < nseg ? kOwnSeg : -1);  // the last segment runs to the end
+      work.push_back(nseg > 1 ? (int32_t)(nslots + k) : -1);
+    }
+    if (nseg > 1) nslots += nseg;
+  }
+}
 
 hipError_t launch_gather(const Plan &p, const void *grid, void *f) {
   if (p.prec == SGL_F64) {

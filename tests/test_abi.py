@@ -80,13 +80,27 @@ def test_plan_rejects_bad_arguments(B, sigma, q, prec, flags, M):
     assert h.value is None
 
 
-@pytest.mark.parametrize("B", [7, 13, 11])
-def test_plan_rejects_fft_lengths_with_large_prime_factors(B):
-    """The FFT handles lengths 2^a 3^b 5^c; sigma * 2B with another prime
-    factor is refused on the host, before any device call."""
+@pytest.mark.parametrize("B,sigma", [(171, 3), (129, 4), (256, 4)])
+def test_plan_rejects_oversized_fft_grids(B, sigma):
+    """FFT lengths are sigma n_j or the next even length whose factors are 2, 3
+    and 5; grids beyond 2048 x 1024 x 1024 are refused on the host, before any
+    device call."""
     sgl = _lib()
     L = sgl.lib()
-    prm = sgl.SglParams(B, 2, 3, 0.0, 0, 0)
+    prm = sgl.SglParams(B, sigma, 3, 0.0, 0, 0)
+    h = ctypes.c_void_p(123)
+    st = L.sgl_plan(ctypes.byref(h), ctypes.byref(prm), 10, ctypes.c_void_p(0x1000), None)
+    assert st == sgl.SGL_E_UNSUPPORTED
+    assert h.value is None
+
+
+@pytest.mark.parametrize("B", [49, 64])
+def test_split16_conversion_refused_above_its_bandwidth(B):
+    """The FP16 hi/lo conversion products miss 1e-5 at B = 64: bandwidths above
+    SGL_CONV_SPLIT16_MAX_B are refused on the host, before any device call."""
+    sgl = _lib()
+    L = sgl.lib()
+    prm = sgl.SglParams(B, 2, 6, 0.0, 1, sgl.SGL_FLAG_CONV_SPLIT16)
     h = ctypes.c_void_p(123)
     st = L.sgl_plan(ctypes.byref(h), ctypes.byref(prm), 10, ctypes.c_void_p(0x1000), None)
     assert st == sgl.SGL_E_UNSUPPORTED

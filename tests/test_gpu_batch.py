@@ -134,3 +134,35 @@ def test_batch_rejects_repeated_and_profiled_plans():
     b.run()
     torch.cuda.synchronize()
     b.close()
+
+
+def test_batch_with_padded_fft_lengths():
+    """Bandwidths whose FFT lengths are padded (B = 17, 23, 31, 61) in one
+    batch: the replay equals each plan's eager calls bit for bit and matches
+    the direct sum on sampled points."""
+    import paper_1809_10786_amd as sgl
+
+    specs = [(17, 3_000), (23, 5_000), (31, 2_000), (61, 4_000)]
+    plans, pts, fh, ys = [], [], [], []
+    for k, (B, M) in enumerate(specs):
+        p = wl.mixed_points(M, 700 + k)
+        pts.append(p)
+        plans.append(sgl.Plan(torch.from_numpy(p).to("cuda", torch.float64), B))
+        fh.append(torch.from_numpy(wl.coefficients(B, 720 + k, decay=1.0)).to("cuda", torch.complex128))
+        ys.append(torch.from_numpy(wl.samples(M, 740 + k)).to("cuda", torch.complex128))
+    outs = [torch.empty(p.M, dtype=torch.complex128, device="cuda") for p in plans]
+    ghs = [torch.empty(p.nc, dtype=torch.complex128, device="cuda") for p in plans]
+    b = sgl.Batch(plans, fh, outs, ys, ghs, nstreams=4)
+    b.run()
+    torch.cuda.synchronize()
+    ef, ea = eager(plans, fh, ys)
+    for k, (B, M) in enumerate(specs):
+        assert torch.equal(outs[k], ef[k]) and torch.equal(ghs[k], ea[k]), B
+        idx = np.sort(np.random.default_rng(750 + k).choice(M, 300, replace=False))
+        f0 = oracle.direct_forward(B, pts[k][idx], fh[k].cpu().numpy())
+        e = float(np.linalg.norm(outs[k].cpu().numpy()[idx] - f0) / np.linalg.norm(f0))
+        say(f"padded batch B={B} N0={plans[k].info()['N0']}: forward on 300 points {e:.3g}")
+        assert e < 2e-6
+    b.close()
+    for p in plans:
+        p.close()

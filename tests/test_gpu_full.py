@@ -12,10 +12,11 @@
     summation order);
   - the adjoint identity <Lambda fhat, y> = <fhat, Lambda^H y> with every
     point;
-* the FP32 NFFT stage (matrix-core gather and spread, tiles of 8^3 cells)
-  against the FP64 stepwise Gaussian NFFT: several tiles with ragged point
-  counts, one tile holding more than one chunk of points, all-zero input and
-  inputs scaled by 2^+-80.
+* the NFFT stage on the matrix-core gather and spread (tiles of 8^3 cells;
+  FP16 hi/lo products for FP32 plans, FP64 products for FP64 plans) against
+  the FP64 stepwise Gaussian NFFT: several tiles with ragged point counts,
+  one tile holding more than one chunk of points, all-zero input and inputs
+  scaled by 2^+-80.
 Tolerances: FP32 1e-5 relative (l2 and max), FP64 at q=6 2e-6 (the Gaussian
 window's truncation error, Theorem 2.7), identity 2e-6 (FP32) / 1e-12 (FP64)
 relative to |y| |Lambda fhat|.
@@ -69,8 +70,9 @@ def check_workload(name, prec, seed, nsample, tol, idtol):
     say(f"full {name} {prec} B={B} M={M} q={w['q']}")
     rdt, cdt = (torch.float64, torch.complex128) if prec == "f64" else (torch.float32, torch.complex64)
     p = sgl.Plan(dev(pts, rdt), B, sigma=w["sigma"], q=w["q"], precision=prec)
-    if prec == "f32":
-        assert p.info()["gather_mode"] == 2  # the matrix-core gather and spread
+    if w["q"] <= 6:
+        # the matrix-core gather and spread: FP16 hi/lo for FP32 plans, FP64 otherwise
+        assert p.info()["gather_mode"] == (2 if prec == "f32" else 3)
     pu, fhu, yu = as_used(pts, prec), as_used(fh, prec), as_used(y, prec)
     f = host(p.forward(dev(fh, cdt)))
     idx = np.sort(np.random.default_rng(seed + 7).choice(M, min(nsample, M), replace=False))
@@ -130,32 +132,37 @@ def stage_points(seed):
     return np.concatenate([a, c], axis=0)
 
 
+@pytest.mark.parametrize("prec", ["f32", "f64"])
 @pytest.mark.parametrize("B", [8, 12])
-def test_fp32_nfft_stage_matrix_cores(B):
+def test_nfft_stage_matrix_cores(B, prec):
+    """The matrix-core gather and spread (FP16 hi/lo for FP32 plans at 1e-5,
+    FP64 for FP64 plans at 1e-11) against the stepwise NFFT."""
     import paper_1809_10786_amd as sgl
 
     q = 6
     pts = stage_points(50 + B)
     rho = 1.1 * np.linalg.norm(pts, axis=1).max()
-    say(f"fp32 nfft stage B={B} M={len(pts)}")
-    p = sgl.Plan(dev(pts, torch.float32), B, q=q, rho=rho, precision="f32")
+    say(f"{prec} nfft stage B={B} M={len(pts)}")
+    rdt, cdt = (torch.float64, torch.complex128) if prec == "f64" else (torch.float32, torch.complex64)
+    tol = 1e-11 if prec == "f64" else 1e-5
+    p = sgl.Plan(dev(pts, rdt), B, q=q, rho=rho, precision=prec)
     info = p.info()
-    assert info["gather_mode"] == 2 and (info["L0"], info["L1"], info["L2"]) == (8, 8, 8)
-    t = sw.x_tilde(as_used(pts, "f32"), p.rho)
+    assert info["gather_mode"] == (3 if prec == "f64" else 2) and (info["L0"], info["L1"], info["L2"]) == (8, 8, 8)
+    t = sw.x_tilde(as_used(pts, prec), p.rho)
     rng = np.random.default_rng(60 + B)
-    eta = as_used(rng.standard_normal(p.eta_shape) + 1j * rng.standard_normal(p.eta_shape), "f32")
-    y = as_used(wl.samples(len(pts), 70 + B), "f32")
+    eta = as_used(rng.standard_normal(p.eta_shape) + 1j * rng.standard_normal(p.eta_shape), prec)
+    y = as_used(wl.samples(len(pts), 70 + B), prec)
     f0 = sw.nfft(eta, t, 2, q)
     e0 = sw.nfft_adjoint(y, t, p.eta_shape, 2, q).reshape(-1)
     for scale in (1.0, 2.0 ** 80, 2.0 ** -80):
-        f = host(p.nfft_forward(dev(eta * scale, torch.complex64))) / scale
-        e = host(p.nfft_adjoint(dev(y * scale, torch.complex64))).reshape(-1) / scale
+        f = host(p.nfft_forward(dev(eta * scale, cdt))) / scale
+        e = host(p.nfft_adjoint(dev(y * scale, cdt))).reshape(-1) / scale
         say(f"  scale {scale:.3g}: forward {rel(f, f0):.3g} / {relinf(f, f0):.3g}, "
             f"adjoint {rel(e, e0):.3g} / {relinf(e, e0):.3g}")
-        assert rel(f, f0) < 1e-5 and relinf(f, f0) < 1e-5
-        assert rel(e, e0) < 1e-5 and relinf(e, e0) < 1e-5
-    z = host(p.nfft_forward(torch.zeros(p.eta_shape, dtype=torch.complex64, device="cuda")))
+        assert rel(f, f0) < tol and relinf(f, f0) < tol
+        assert rel(e, e0) < tol and relinf(e, e0) < tol
+    z = host(p.nfft_forward(torch.zeros(p.eta_shape, dtype=cdt, device="cuda")))
     assert not np.any(z)
-    z = host(p.nfft_adjoint(torch.zeros(len(pts), dtype=torch.complex64, device="cuda")))
+    z = host(p.nfft_adjoint(torch.zeros(len(pts), dtype=cdt, device="cuda")))
     assert not np.any(z)
     p.close()

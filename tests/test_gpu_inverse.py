@@ -9,7 +9,10 @@ least-squares solve of the oracle's Lambda.
 * the paper's grid G_N (Section 8) with kappa = 6, N = 20 and the mid-point
   rule weights w_i = (2 kappa / N)^3 e^{-|x_i|^2} as the weights of CGNR
   (B = 8): converges, and in fewer iterations than W = I;
-* an FP32 plan (vectors FP32, scalars FP64): relative error <= 1e-4.
+* an FP32 plan (vectors FP32, scalars FP64): relative error <= 1e-4;
+* CGNE for fewer samples than coefficients (normal equations of the second
+  kind, Section 2): the residual falls below 1e-10 and the result is the
+  minimum-norm solution (a dense least-squares solve of the oracle's Lambda).
 """
 import numpy as np
 import pytest
@@ -98,4 +101,25 @@ def test_cgnr_fp32_plan():
     x, info = p.cgnr(dev(y, torch.complex64), maxiter=300, tol=1e-6)
     say(f"cgnr fp32: {info}, vs truth {rel(host(x), fh):.3g}")
     assert rel(host(x), fh) < 1e-4
+    p.close()
+
+
+def test_cgne_minimum_norm_solution():
+    import paper_1809_10786_amd as sgl
+
+    B, M = 8, 100  # Nc = 204 > M; cond(Lambda) about 4e3 on these points
+    pts = wl.gaussian_points(M, 160)
+    fstar = wl.coefficients(B, 161)
+    lam = sw.sgl_basis(B, pts)
+    y = lam @ fstar
+    say(f"cgne B={B} M={M} Nc={lam.shape[1]}")
+    p = sgl.Plan(dev(pts, torch.float64), B, q=12)
+    x, info = p.cgne(dev(y, torch.complex128), maxiter=5000, tol=1e-11)
+    x = host(x)
+    xmin = np.linalg.lstsq(lam, y, rcond=None)[0]  # minimum-norm solution
+    say(f"  iterations {info['iterations']} residual {info['rel_residual']:.3g} "
+        f"against the minimum-norm solution {rel(x, xmin):.3g}")
+    assert info["rel_residual"] <= 1e-11
+    assert rel(lam @ x, y) < 1e-9
+    assert rel(x, xmin) < 1e-6
     p.close()

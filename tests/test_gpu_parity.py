@@ -6,7 +6,9 @@
 * end to end against the direct sum (Def. 1.3) within the NFFT tolerance;
 * the adjoint identity <Lambda fhat, y> = <fhat, Lambda^H y> of the fast pair;
 * edge cases: origin, z axis, phi near 2 pi, r = rho, M = 1, B = 2, user rho,
-  and the documented error codes.
+  and the documented error codes;
+* bandwidths whose FFT lengths are padded to the next length with factors 2,
+  3 and 5 (B = 7, 13, 17, 23, 31, 61).
 Tolerances: FP64 stage pins 1e-11 (relative l2); FP64 end to end at q=16
 1e-10 (the paper reports ~1e-10 at q=16, Section 8); FP32 end to end 1e-5.
 """
@@ -150,6 +152,40 @@ def test_b8_m1e4_f64_against_direct_sum():
     g0 = oracle.direct_adjoint(w["B"], pts, y)
     say(f"  adjoint {rel(g, g0):.3g} / {relinf(g, g0):.3g}")
     assert rel(g, g0) < 1e-10 and relinf(g, g0) < 1e-10
+
+
+def _smooth235(v):
+    for f in (2, 3, 5):
+        while v % f == 0:
+            v //= f
+    return v == 1
+
+
+@pytest.mark.parametrize("B", [7, 13, 17, 23, 31, 61])
+def test_padded_fft_lengths_against_direct_sum(B):
+    """Bandwidths whose oversampled lengths sigma n_j have a prime factor above
+    5 run on the next even length with factors 2, 3 and 5 (effective sigma
+    above 2, the window's lambda kept): forward and the adjoint of dense
+    samples against the direct sum."""
+    M, q = 3000, 8
+    pts = wl.gaussian_points(M, 150 + B)
+    fh = wl.coefficients(B, 151 + B)
+    y = wl.samples(M, 152 + B)
+    p = plan(pts, B, q=q)
+    info = p.info()
+    for j, n in enumerate((4 * B, 2 * B, 2 * B)):
+        N = info[f"N{j}"]
+        assert N % 2 == 0 and N >= 2 * n and _smooth235(N)
+        assert all(not _smooth235(v) for v in range(2 * n, N, 2)), (j, N)
+    assert not all(info[f"N{j}"] == 2 * n for j, n in enumerate((4 * B, 2 * B, 2 * B)))
+    f = host(p.forward(dev(fh, torch.complex128)))
+    f0 = oracle.direct_forward(B, pts, fh)
+    g = host(p.adjoint(dev(y, torch.complex128)))
+    g0 = oracle.direct_adjoint(B, pts, y)
+    say(f"padded B={B} N={info['N0']},{info['N1']},{info['N2']}: forward {rel(f, f0):.3g} / {relinf(f, f0):.3g}, "
+        f"adjoint {rel(g, g0):.3g} / {relinf(g, g0):.3g}")
+    assert rel(f, f0) < 1e-7 and relinf(f, f0) < 1e-7
+    assert rel(g, g0) < 1e-7 and relinf(g, g0) < 1e-7
 
 
 def test_f32_high_cutoff_against_direct_sum():

@@ -9,7 +9,10 @@ and FP32 accumulation, against the oracle.
   1e6 workload): forward at sampled points and adjoint on a subset against the
   direct sum, relative l2 <= 1e-5 (measured 4.8e-7 / 4.6e-7; the FP64 products
   give 2.6e-7 / 2.8e-7);
-* the adjoint identity of the split pair, <= 2e-6 relative.
+* the adjoint identity of the split pair, <= 2e-6 relative;
+* at B = 48, the largest bandwidth the flag accepts, on 3,000 points of the
+  anisotropic mixture (rho about 6, where the sums cancel most): forward and
+  the adjoint of dense samples against the direct sum, relative l2 <= 1e-5.
 The pointwise error of points where |f| is far below its maximum is larger
 than with the FP64 products (the sums cancel; see the design notes), so this
 form is opt-in.
@@ -89,4 +92,21 @@ def test_split_conversion_b32_mixed_f32():
     lhs, rhs = np.vdot(yu, f), np.vdot(ga, fhu)
     say(f"  identity {abs(lhs - rhs) / (np.linalg.norm(yu) * np.linalg.norm(f)):.3g}")
     assert abs(lhs - rhs) < 2e-6 * np.linalg.norm(yu) * np.linalg.norm(f)
+    p.close()
+
+
+def test_split_conversion_largest_bandwidth():
+    import paper_1809_10786_amd as sgl
+
+    B, M = 48, 3000
+    pts = wl.mixture_points(M, 170).astype(np.float32).astype(np.float64)
+    fh = wl.coefficients(B, 171).astype(np.complex64).astype(np.complex128)
+    y = wl.samples(M, 172).astype(np.complex64).astype(np.complex128)
+    p = sgl.Plan(dev(pts, torch.float32), B, precision="f32", conv_split16=True)
+    f = host(p.forward(dev(fh, torch.complex64)))
+    g = host(p.adjoint(dev(y, torch.complex64)))
+    f0 = oracle.direct_forward(B, pts, fh)
+    g0 = oracle.direct_adjoint(B, pts, y)
+    say(f"split16 B={B} rho={p.rho:.2f}: forward {rel(f, f0):.3g}, adjoint {rel(g, g0):.3g}")
+    assert rel(f, f0) < 1e-5 and rel(g, g0) < 1e-5
     p.close()

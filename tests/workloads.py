@@ -48,6 +48,15 @@ def ball_points(M, radius, seed):
     return d * r[:, None]
 
 
+def ball_points_centered(M, radius, seed):
+    """Points in the ball of the given radius with radius * U^(1/2) as their
+    distance from the origin: point density falling as 1/r towards the rim."""
+    rng = np.random.default_rng(seed)
+    d = rng.standard_normal((M, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    return d * (radius * rng.uniform(0, 1, M) ** 0.5)[:, None]
+
+
 def mixed_points(M, seed, frac_ball=0.1, radius=4.0):
     """(1 - frac_ball) M Gaussian points plus frac_ball M uniform in a ball."""
     mb = int(round(M * frac_ball))
@@ -97,6 +106,9 @@ WORKLOADS = {
     "b64_m4e6_f64_q14": dict(B=64, M=4_000_000, points="gaussian", decay=1.5, sigma=2, q=14, prec="f64"),
     # Inverse transform: B=32, M=3e5 FP64 points in eight clusters (Dirichlet(1) weights), n^-1.5, q=6.
     "b32_m3e5_clustered_f64": dict(B=32, M=300_000, points="clustered8", decay=1.5, sigma=2, q=6, prec="f64"),
+    # Inverse transform where a normal residual of 1e-6 is reachable: B=12, M=2e4 FP64 points
+    # covering the ball of radius 5, density falling as 1/r, n^-1.5, q=8.
+    "b12_m2e4_centered5_f64": dict(B=12, M=20_000, points="centered5", decay=1.5, sigma=2, q=8, prec="f64"),
     # B=48, M=2e6 FP32 points from a 3-component anisotropic Gaussian mixture, n^-1.5, q=6.
     "b48_m2e6_f32": dict(B=48, M=2_000_000, points="aniso3", decay=1.5, sigma=2, q=6, prec="f32"),
 }
@@ -111,6 +123,8 @@ def make_points(kind, M, seed):
         return mixture_points(M, seed)
     if kind == "clustered8":
         return clustered_points(M, seed)
+    if kind.startswith("centered"):
+        return ball_points_centered(M, float(kind[8:]), seed)
     if kind.startswith("ball"):
         return ball_points(M, float(kind[4:]), seed)
     raise ValueError(kind)
@@ -126,22 +140,10 @@ def workload(name, seed=0, M=None):
     return w, pts, fhat, y
 
 
-def _smooth235(v):
-    for p in (2, 3, 5):
-        while v % p == 0:
-            v //= p
-    return v == 1
-
-
-# Bandwidths whose FFT lengths 4B and 8B (sigma = 2) factor into 2, 3 and 5.
-SMOOTH_B = tuple(b for b in range(2, 257) if _smooth235(4 * b) and _smooth235(8 * b))
-
-
 def batch_specs(n=64, seed=0, b_lo=16, b_hi=64, m_lo=1e5, m_hi=2e6):
-    """(B, M) of a batch: B uniform over the supported bandwidths in [b_lo, b_hi],
-    M log-uniform in [m_lo, m_hi]."""
+    """(B, M) of a batch: B uniform in [b_lo, b_hi], M log-uniform in [m_lo, m_hi]."""
     rng = np.random.default_rng(seed)
-    bs = [b for b in SMOOTH_B if b_lo <= b <= b_hi]
+    bs = list(range(b_lo, b_hi + 1))
     B = rng.choice(bs, n)
     M = np.exp(rng.uniform(np.log(m_lo), np.log(m_hi), n)).astype(np.int64)
     return [(int(b), int(m)) for b, m in zip(B, M)]
