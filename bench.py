@@ -64,14 +64,14 @@ def parse():
     return ap.parse_args()
 
 
-PROFILE_COMMAND = ("rocprofv3 {mode} -T -f csv -d gpurun_out/prof_{tag} -o {tag} -- python3 bench.py {workload}--steps {steps} "
-                   "--warmup 1 --no-cpu-baseline --check-points 0 --copy-calibration 256 --sequential")
+PROFILE_COMMAND = ("rocprofv3 {mode} -T -f csv -d gpurun_out/prof_{name}_{tag} -o {tag} -- python3 bench.py "
+                   "--workload {name} --steps {steps} --warmup 1 --no-cpu-baseline --check-points 0 "
+                   "--copy-calibration 256 --sequential")
 
 
 def profile_command(workload, **kw):
     """The rocprofv3 command line of one profiled run of this script."""
-    wa = "" if workload == "b64_m4e6_f64" else f"--workload {workload} "
-    return PROFILE_COMMAND.format(workload=wa, **kw)
+    return PROFILE_COMMAND.format(name=workload, **kw)
 
 
 def spread_flops(q):
@@ -144,7 +144,7 @@ def accuracy(B, plan, pts_used, fh_used, f_gpu, y, prec, m, torch, cdt):
 # ---------------------------------------------------------------- profiles
 
 STAGE_KERNEL_VALU = {"gather": "k_gather_tiled", "scatter": "k_spread_rows", "fold": "k_fold_staging"}
-STAGE_KERNEL_DIRECT = {"gather": "k_gather_direct", "scatter": "k_scatter_owned"}
+STAGE_KERNEL_DIRECT = {"gather": "k_gather_slab", "scatter": "k_scatter_owned", "fold": "k_fold_owned"}
 STAGE_KERNEL_MFMA = {"gather": "k_gather_mfma", "scatter": "k_spread_mfma", "fold": "k_fold_tiles8"}
 STAGE_KERNEL_MFMA64 = {"gather": "k_gather_tiled", "scatter": "k_spread_mfma64", "fold": "k_fold_tiles8"}
 KERNEL_SOURCE = {"k_gather_tiled": "sgl_spread.hip", "k_spread_rows": "sgl_spread.hip",

@@ -285,7 +285,8 @@ sgl_status sgl_plan_rho(sgl_plan_t plan, double *rho);
 /* Informational: number of points, FFT grid sigma*n, stored (pruned) grid
  * extents, gather tile edges, and bytes of device workspace.  info must
  * hold 12 int64 values: {M, N0, N1, N2, E0, E1, E2, L0, L1, L2, bytes,
- * gather_mode (0 = LDS tiles, 1 = direct gather and cell-owned scatter,
+ * gather_mode (0 = LDS tiles, 1 = wide windows: the box streamed through LDS
+ * in slabs for the gather, cell-owned blocks for the scatter,
  * 2 = LDS tiles with the FP16 hi/lo matrix-core gather and spread of FP32
  * plans, 3 = LDS tiles with the FP64 matrix-core spread of FP64 plans)}. */
 sgl_status sgl_plan_info(sgl_plan_t plan, int64_t info[12]);

@@ -186,6 +186,12 @@ sgl_status setup_geometry(Plan &p) {
   // row (at most 512) and a box edge of 4 or 8 base cells along dimension 2
   if ((size_t)(L[0] + 2 * p.q - 1) * (L[1] + 2 * p.q - 1) > 512 || p.q > 8 || (L[2] != 4 && L[2] != 8))
     p.gather_mode = 1;
+  if (p.gather_mode == 1) {
+    // wide windows: tiles of 8^3 base cells, the box streamed through LDS in
+    // slabs of four dimension-0 planes (k_gather_slab; four planes of the box
+    // fit the budget for every q <= 16)
+    L[0] = L[1] = L[2] = 8;
+  }
   p.ntiles = 1;
   for (int j = 0; j < 3; ++j) {
     p.L[j] = std::min(L[j], p.NB[j]);

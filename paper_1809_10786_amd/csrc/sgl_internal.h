@@ -111,7 +111,7 @@ struct Plan {
   // point bins (gather tiles) over base cells: edge L, count T, base range NB
   int L[3], T[3], NB[3], X[3];
   int64_t ntiles = 0;
-  int gather_mode = 0;  // 0: LDS tiles, 1: direct from the grid
+  int gather_mode = 0;  // 0: LDS tiles, 1: box streamed in slabs and cell-owned scatter
   // tiled gather in 256-thread workgroups, leaving room on each CU for the
   // workgroups of a concurrent scatter
   bool gather_narrow = false;

@@ -13,8 +13,9 @@
 //  * gather (tiled): one workgroup per chunk of points of one tile of base
 //    cells; the tile's window box is staged in LDS and each thread evaluates
 //    one point at a time.
-//  * gather (direct): each thread evaluates one point reading the grid
-//    through the cache (used when the window box does not fit in LDS).
+//  * gather (slabs): for windows too wide for the whole box in LDS, the box
+//    of a chunk's tile is streamed through LDS a few dimension-0 planes at a
+//    time, the points' partial sums kept in registers.
 //  * scatter (tiled): one workgroup per chunk accumulates all taps of its
 //    points into the tile's window box, held as register rows, and writes the
 //    box to a staging slot of its own; a fold pass then sums, for every stored
@@ -436,48 +437,107 @@ __global__ __launch_bounds__(GatherShape<Q2>::threads) void k_gather_mfma(const 
   }
 }
 
-// ---------------------------------------------------------------- gather, direct
+// ---------------------------------------------------------------- gather, slabs
+
+// Gather for windows too wide for the whole box of a tile in LDS (large q):
+// one workgroup per chunk streams the box through LDS in slabs of kSlab
+// dimension-0 planes.  The chunk's points are taken 64 at a time, four
+// adjacent lanes per point, lane `sub` summing the rows t1 = sub, sub + 4, ...
+// of every plane of the point's window; the partial sums stay in registers
+// across the slabs and the four lanes add them as (p0 + p1) + (p2 + p3).
+constexpr int kSlab = 4;
+constexpr int kSlabThreads = 256;
 
 template <class R, int Q2>
-__global__ __launch_bounds__(256) void k_gather_direct(const cplx<R> *__restrict__ grid,
-                                                       const PointRec<R> *__restrict__ pts,
-                                                       const int32_t *__restrict__ perm, int64_t M, Geom g,
-                                                       R inv2lam, cplx<R> *__restrict__ f) {
+__global__ __launch_bounds__(kSlabThreads) void k_gather_slab(const cplx<R> *__restrict__ grid,
+                                                              const PointRec<R> *__restrict__ pts,
+                                                              const int32_t *__restrict__ perm,
+                                                              const int32_t *__restrict__ chunks, Geom g,
+                                                              R inv2lam, cplx<R> *__restrict__ f) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  cplx<R> *slab = (cplx<R> *)smem;  // [kSlab][X1][X2]
   constexpr int q = Q2 / 2;
-  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (k >= M) return;
-  const PointRec<R> pr = pts[k];
-  const int b0 = cell0(pr.cell), b1 = cell1(pr.cell), b2 = cell2(pr.cell);
-  R w2[Q2];
-  int i2[Q2];
-#pragma unroll
-  for (int t = 0; t < Q2; ++t) {
-    w2[t] = gauss<R>(pr.frac[2] + (R)(q - 1 - t), inv2lam);
-    i2[t] = stored_index(b2 - q + 1 + t, 2, g);
-  }
-  R ar = 0, ai = 0;
-  for (int t0 = 0; t0 < Q2; ++t0) {
-    const int s0 = stored_index(b0 - q + 1 + t0, 0, g);
-    const R w0 = gauss<R>(pr.frac[0] + (R)(q - 1 - t0), inv2lam);
-    R br = 0, bi = 0;
-    for (int t1 = 0; t1 < Q2; ++t1) {
-      const int s1 = stored_index(b1 - q + 1 + t1, 1, g);
-      const R w1 = gauss<R>(pr.frac[1] + (R)(q - 1 - t1), inv2lam);
-      const cplx<R> *row = grid + ((size_t)s0 * g.E[1] + s1) * g.E[2];
-      R cr = 0, ci = 0;
-#pragma unroll
-      for (int t2 = 0; t2 < Q2; ++t2) {
-        const cplx<R> v = row[i2[t2]];
-        cr += w2[t2] * v.re;
-        ci += w2[t2] * v.im;
-      }
-      br += w1 * cr;
-      bi += w1 * ci;
+  constexpr int T1 = (Q2 + 3) / 4;  // rows per lane
+  const int tidx = chunks[3 * blockIdx.x];
+  const int start = chunks[3 * blockIdx.x + 1];
+  const int count = chunks[3 * blockIdx.x + 2];
+  const int c2 = tidx % g.T[2];
+  const int c1 = (tidx / g.T[2]) % g.T[1];
+  const int c0 = tidx / (g.T[2] * g.T[1]);
+  const int X0 = g.X[0], X1 = g.X[1], X2 = g.X[2];
+  const int wb0 = c0 * g.L[0] - q + 1, wb1 = c1 * g.L[1] - q + 1, wb2 = c2 * g.L[2] - q + 1;
+  const int sub = threadIdx.x & 3;
+  for (int pass = 0; pass < count; pass += kSlabThreads / 4) {
+    const int idx = pass + (int)threadIdx.x / 4;
+    const bool valid = idx < count;
+    PointRec<R> pr;
+    pr.frac[0] = pr.frac[1] = pr.frac[2] = 0;
+    pr.cell = 0;
+    int o0 = 1 << 20, o1 = 0, o2 = 0;  // no plane of any slab when invalid
+    if (valid) {
+      pr = pts[start + idx];
+      o0 = cell0(pr.cell) - c0 * g.L[0];
+      o1 = cell1(pr.cell) - c1 * g.L[1];
+      o2 = cell2(pr.cell) - c2 * g.L[2];
     }
-    ar += w0 * br;
-    ai += w0 * bi;
+    R w1[T1], w2[Q2];
+#pragma unroll
+    for (int t = 0; t < T1; ++t) {
+      const int t1 = sub + 4 * t;
+      w1[t] = t1 < Q2 ? gauss<R>(pr.frac[1] + (R)(q - 1 - t1), inv2lam) : (R)0;
+    }
+#pragma unroll
+    for (int t = 0; t < Q2; ++t) w2[t] = gauss<R>(pr.frac[2] + (R)(q - 1 - t), inv2lam);
+    R ar = 0, ai = 0;
+    for (int s0 = 0; s0 < X0; s0 += kSlab) {
+      const int np = min(kSlab, X0 - s0);
+      __syncthreads();  // the previous slab is consumed
+      for (int e = threadIdx.x; e < np * X1 * X2; e += kSlabThreads) {
+        const int i2 = e % X2, r = e / X2, i1 = r % X1, ip = r / X1;
+        const int sa = stored_index(wb0 + s0 + ip, 0, g), sb = stored_index(wb1 + i1, 1, g),
+                  sc = stored_index(wb2 + i2, 2, g);
+        R vr = 0, vi = 0;
+        if (sa >= 0 && sb >= 0 && sc >= 0) {
+          const cplx<R> v = grid[((size_t)sa * g.E[1] + sb) * g.E[2] + sc];
+          vr = v.re;
+          vi = v.im;
+        }
+        slab[e] = cplx<R>{vr, vi};
+      }
+      __syncthreads();
+      // planes of this slab inside the point's window
+      const int p_lo = max(s0, o0), p_hi = min(s0 + np, o0 + Q2);
+      for (int i0 = p_lo; i0 < p_hi; ++i0) {
+        const R w0 = gauss<R>(pr.frac[0] + (R)(q - 1 - (i0 - o0)), inv2lam);
+        const cplx<R> *plane = slab + (size_t)(i0 - s0) * X1 * X2 + o2;
+        R br = 0, bi = 0;
+#pragma unroll
+        for (int t = 0; t < T1; ++t) {
+          const int t1 = sub + 4 * t;
+          if (t1 < Q2) {
+            const cplx<R> *row = plane + (size_t)(o1 + t1) * X2;
+            R cr = 0, ci = 0;
+#pragma unroll
+            for (int t2 = 0; t2 < Q2; ++t2) {
+              const cplx<R> v = row[t2];
+              cr += w2[t2] * v.re;
+              ci += w2[t2] * v.im;
+            }
+            br += w1[t] * cr;
+            bi += w1[t] * ci;
+          }
+        }
+        ar += w0 * br;
+        ai += w0 * bi;
+      }
+    }
+    // (p0 + p1) + (p2 + p3) in every lane of the group
+    ar += __shfl_xor(ar, 1, 64);
+    ai += __shfl_xor(ai, 1, 64);
+    ar += __shfl_xor(ar, 2, 64);
+    ai += __shfl_xor(ai, 2, 64);
+    if (valid && sub == 0) f[perm[start + idx]] = cplx<R>{ar, ai};
   }
-  f[perm[k]] = cplx<R>{ar, ai};
 }
 
 // ---------------------------------------------------------------- gradient in x
@@ -1548,8 +1608,9 @@ hipError_t gather_q(const Plan &p, const void *grid, void *f) {
     k_gather_tiled<R, Q2><<<(unsigned)p.nchunks, narrow ? 256 : GatherTiled<Q2>::threads, lds, p.stream>>>(
         (const cplx<R> *)grid, (const PointRec<R> *)p.pts, p.perm, p.chunks, g, inv2lam, (cplx<R> *)f);
   } else {
-    k_gather_direct<R, Q2><<<(unsigned)((p.M + 255) / 256), 256, 0, p.stream>>>(
-        (const cplx<R> *)grid, (const PointRec<R> *)p.pts, p.perm, p.M, g, inv2lam, (cplx<R> *)f);
+    const size_t lds = (size_t)kSlab * p.X[1] * p.X[2] * sizeof(cplx<R>);
+    k_gather_slab<R, Q2><<<(unsigned)p.nchunks, kSlabThreads, lds, p.stream>>>(
+        (const cplx<R> *)grid, (const PointRec<R> *)p.pts, p.perm, p.chunks, g, inv2lam, (cplx<R> *)f);
   }
   return hipGetLastError();
 }

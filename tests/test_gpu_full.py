@@ -107,7 +107,7 @@ def test_b64_m4e6_f64():
 
 
 def test_b64_m4e6_f64_q14():
-    """The high-accuracy cutoff q = 14 (cell-owned scatter, direct gather)."""
+    """The high-accuracy cutoff q = 14 (cell-owned scatter, slab-streamed gather)."""
     check_workload("b64_m4e6_f64_q14", "f64", 17, NFWD, 1e-10, 1e-12)
 
 

@@ -189,7 +189,7 @@ def test_padded_fft_lengths_against_direct_sum(B):
 
 
 def test_f32_high_cutoff_against_direct_sum():
-    """An FP32 plan with q = 10 (direct gather, cell-owned scatter): forward and
+    """An FP32 plan with q = 10 (slab-streamed gather, cell-owned scatter): forward and
     the adjoint of dense samples within 1e-5 of the direct sum."""
     B, M = 16, 5000
     pts = wl.gaussian_points(M, 140)
