@@ -900,7 +900,10 @@ sgl_status sgl_forward_adjoint(sgl_plan_t plan, const void *fhat_dev, void *f_de
   Plan &a = plan->adj;
   SGL_TRY(hipEventRecord(plan->fork, p.stream));
   SGL_TRY(hipStreamWaitEvent(a.stream, plan->fork, 0));
-  p.gather_narrow = true;  // the adjoint's scatter shares the CUs
+  // the adjoint's scatter shares the CUs: the narrow gather leaves it registers
+  // (the FP64 matrix-core scatter needs a CU's LDS to itself, so there the
+  // wide gather is kept)
+  p.gather_narrow = !p.mfma64;
   st = plan_forward(p, fhat_dev, f_dev);
   p.gather_narrow = false;
   const sgl_status sa = plan_adjoint(a, y_dev, ghat_dev);

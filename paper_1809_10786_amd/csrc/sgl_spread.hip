@@ -737,7 +737,7 @@ __global__ __launch_bounds__(kSpread64Threads) void k_spread_mfma64(const cplx<d
   __shared__ double sfr[3][kSB64];
   __shared__ int so[3][kSB64];
   __shared__ cplx<double> sy[kSB64];
-  __shared__ int srb[kSB64 / 4][2];       // row blocks a K step of 4 points meets
+  __shared__ int srb[kSB64 / 4][3];       // row blocks a K step of 4 points meets, column blocks it needs
 
   const int tidx = chunks[3 * blockIdx.x];
   const int start = chunks[3 * blockIdx.x + 1];
@@ -822,24 +822,28 @@ __global__ __launch_bounds__(kSpread64Threads) void k_spread_mfma64(const cplx<d
     }
     if ((int)threadIdx.x < kSB64 / 4) {
       // rows i0 * X + i1 with i0 outside [min o0, max o0 + Q2) of a K step's
-      // points have A = 0 there: the step only needs the row blocks between
+      // points have A = 0 there, so the step only needs the row blocks that
+      // meet that range; columns 2 i2 + c with i2 at or past max o2 + Q2 have
+      // B = 0, so it only needs the column blocks below 2 (max o2 + Q2)
       const int k4 = threadIdx.x;
-      int lo = X, hi = 0;
+      int lo = X, hi = 0, hi2 = 0;
       for (int j = 0; j < 4; ++j) {
         const int pp = 4 * k4 + j;
         if (pp < nb) {
           lo = min(lo, so[0][pp]);
           hi = max(hi, so[0][pp]);
+          hi2 = max(hi2, so[2][pp]);
         }
       }
       srb[k4][0] = lo < X ? (lo * X) / 16 : nrb;
       srb[k4][1] = lo < X ? min(nrb, ((hi + Q2) * X + 15) / 16) : nrb;
+      srb[k4][2] = min(NCB, (2 * min(X, hi2 + Q2) + 15) / 16);
     }
     __syncthreads();
     if (b0 + kSB64 < count) fetch(b0 + kSB64);
     // 3. products over the batch, K = 4 points per step
     for (int ks = 0; ks < nb; ks += 4) {
-      const int kr_lo = srb[ks / 4][0], kr_hi = srb[ks / 4][1];
+      const int kr_lo = srb[ks / 4][0], kr_hi = srb[ks / 4][1], kc_hi = srb[ks / 4][2];
       const int pp = ks + kq;  // this lane's point of the K step (A column, B row)
       double bf[NCB];
 #pragma unroll
@@ -852,7 +856,8 @@ __global__ __launch_bounds__(kSpread64Threads) void k_spread_mfma64(const cplx<d
           const int i0 = row / X, i1 = row - (row / X) * X;
           const double a = tw[0][pp][i0] * tw[1][pp][i1];
 #pragma unroll
-          for (int n = 0; n < NCB; ++n) acc[r][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bf[n], acc[r][n], 0, 0, 0);
+          for (int n = 0; n < NCB; ++n)
+            if (n < kc_hi) acc[r][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bf[n], acc[r][n], 0, 0, 0);
         }
       }
     }
