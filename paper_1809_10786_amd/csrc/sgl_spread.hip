@@ -43,6 +43,7 @@ struct Geom {
   int N[3], E[3], lo[3], pruned[3];
   int L[3], T[3], X[3], NB[3];
   int Lo[3], To[3];
+  int S01;  // plane stride of the tiled gather's LDS box, >= X1 X2
 };
 
 __device__ inline int stored_index(int l, int j, const Geom &g) {
@@ -61,18 +62,40 @@ __device__ inline R gauss(R d, R inv2lam) {
 
 // ---------------------------------------------------------------- gather, tiled
 
-// Threads of a tiled-gather workgroup, and lanes that share one point: lane
-// `sub` of a group of four adjacent lanes takes the dimension-0 planes
-// t0 = sub, sub + 4, ... and the group adds the four partial sums as
-// (p0 + p1) + (p2 + p3) with two butterfly exchanges.  Small chunks still keep
-// many lanes busy, and 1,024-thread workgroups read the box in LDS with 16
-// waves per CU.  The narrow form (256 threads) leaves registers for a scatter
-// running beside it on the same CU; the sums, and so the bits, are the same.
+// Tiled gather: a workgroup copies the window box of its tile (X0 x X1 x X2
+// grid values around L0 x L1 x L2 base cells) into LDS once and evaluates
+// its chunk of points there.  Sixteen adjacent lanes share one point as a
+// 4 x 4 grid (a, b) over the rows of the window: lane (a, b) takes the rows
+// (t0, t1) = (a + 4 j0, b + 4 j1) and runs the dimension-2 sums along them,
+// and the sixteen partial sums are added in a fixed butterfly.  The box
+// planes lie S01 >= X1 X2 values apart, with S01 chosen on the host so that at
+// every read the sixteen lanes of a point meet sixteen distinct LDS bank
+// groups (a value is 16 bytes in FP64, 4 banks): the gather is bound by LDS
+// bandwidth, and random per-lane rows cost it a third more in bank conflicts.
+// 1,024-thread workgroups run 16 waves per CU; the narrow form (256 threads)
+// leaves registers for a scatter running beside it on the same CU, with the
+// same sums and so the same bits.
 template <int Q2>
 struct GatherTiled {
   static constexpr int threads = Q2 <= 12 ? 1024 : Q2 <= 16 ? 512 : 256;
 };
-constexpr int kGatherSplit = 4;
+constexpr int kGatherLanes = 16;
+
+// Gaussian window values exp(-u_j^2 / (2 lambda)) at u_j = u - s j for
+// j < n, by the recurrence w_(j+1) = w_j r_j, r_j = exp((2 s u_j - s^2) /
+// (2 lambda)), r_(j+1) = r_j exp(-2 s^2 / (2 lambda)): two exponentials in
+// place of n (FP64; the relative error grows by about one rounding per step).
+template <int n, int s>
+__device__ inline void gauss_run(double u, double inv2lam, double cs, double *w) {
+  double wv = exp(-u * u * inv2lam);
+  double r = exp((2.0 * s * u - (double)(s * s)) * inv2lam);
+#pragma unroll
+  for (int j = 0; j < n; ++j) {
+    w[j] = wv;
+    wv *= r;
+    r *= cs;
+  }
+}
 
 template <class R, int Q2>
 __global__ __launch_bounds__(GatherTiled<Q2>::threads) void k_gather_tiled(const cplx<R> *__restrict__ grid,
@@ -83,14 +106,14 @@ __global__ __launch_bounds__(GatherTiled<Q2>::threads) void k_gather_tiled(const
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   cplx<R> *tile = (cplx<R> *)smem;
   constexpr int q = Q2 / 2;
-  constexpr int S = kGatherSplit;
+  constexpr int J = (Q2 + 3) / 4;  // rows per lane along dimensions 0 and 1
   const int tidx = chunks[3 * blockIdx.x];
   const int start = chunks[3 * blockIdx.x + 1];
   const int count = chunks[3 * blockIdx.x + 2];
   const int c2 = tidx % g.T[2];
   const int c1 = (tidx / g.T[2]) % g.T[1];
   const int c0 = tidx / (g.T[2] * g.T[1]);
-  const int X0 = g.X[0], X1 = g.X[1], X2 = g.X[2];
+  const int X0 = g.X[0], X1 = g.X[1], X2 = g.X[2], S01 = g.S01;
   const int wb0 = c0 * g.L[0] - q + 1, wb1 = c1 * g.L[1] - q + 1, wb2 = c2 * g.L[2] - q + 1;
   for (int e = threadIdx.x; e < X0 * X1 * X2; e += blockDim.x) {
     const int i2 = e % X2, r = e / X2, i1 = r % X1, i0 = r / X1;
@@ -104,32 +127,49 @@ __global__ __launch_bounds__(GatherTiled<Q2>::threads) void k_gather_tiled(const
       vr = v.re;
       vi = v.im;
     }
-    tile[e] = cplx<R>{vr, vi};
+    tile[i0 * S01 + i1 * X2 + i2] = cplx<R>{vr, vi};
   }
   __syncthreads();
-  // the S lanes of a group are adjacent and share k, so a group is active or
-  // inactive as a whole around the exchanges
-  const int sub = threadIdx.x % S;
-  for (int k = start + (int)threadIdx.x / S; k < start + count; k += (int)blockDim.x / S) {
+  // the sixteen lanes of a point are adjacent and share k, so they are active
+  // or inactive together around the exchanges
+  const int sub = threadIdx.x % kGatherLanes, a = sub / 4, b = sub % 4;
+  const R cs1 = exp((R)-2 * inv2lam), cs4 = exp((R)-32 * inv2lam);
+  for (int k = start + (int)threadIdx.x / kGatherLanes; k < start + count;
+       k += (int)blockDim.x / kGatherLanes) {
     const PointRec<R> pr = pts[k];
     const int o0 = cell0(pr.cell) - c0 * g.L[0];
     const int o1 = cell1(pr.cell) - c1 * g.L[1];
     const int o2 = cell2(pr.cell) - c2 * g.L[2];
-    R w1[Q2], w2[Q2];
+    // w0[j] at t0 = a + 4 j, w1[j] at t1 = b + 4 j (zero past the window),
+    // w2[t] at t2 = t; the window value at offset t is gauss(frac + q - 1 - t)
+    R w0[J], w1[J], w2[Q2];
+    if constexpr (std::is_same<R, double>::value) {
+      gauss_run<J, 4>(pr.frac[0] + (double)(q - 1 - a), inv2lam, cs4, w0);
+      gauss_run<J, 4>(pr.frac[1] + (double)(q - 1 - b), inv2lam, cs4, w1);
+      gauss_run<Q2, 1>(pr.frac[2] + (double)(q - 1), inv2lam, cs1, w2);
+    } else {
 #pragma unroll
-    for (int t = 0; t < Q2; ++t) {
-      w1[t] = gauss<R>(pr.frac[1] + (R)(q - 1 - t), inv2lam);
-      w2[t] = gauss<R>(pr.frac[2] + (R)(q - 1 - t), inv2lam);
+      for (int j = 0; j < J; ++j) {
+        w0[j] = gauss<R>(pr.frac[0] + (R)(q - 1 - a - 4 * j), inv2lam);
+        w1[j] = gauss<R>(pr.frac[1] + (R)(q - 1 - b - 4 * j), inv2lam);
+      }
+#pragma unroll
+      for (int t = 0; t < Q2; ++t) w2[t] = gauss<R>(pr.frac[2] + (R)(q - 1 - t), inv2lam);
     }
-    const cplx<R> *base = tile + ((size_t)o0 * X1 + o1) * X2 + o2;
+    if constexpr (Q2 % 4 != 0) {
+      // rows past the window read its last row (inside the box) with weight 0
+      if (a + 4 * (J - 1) >= Q2) w0[J - 1] = 0;
+      if (b + 4 * (J - 1) >= Q2) w1[J - 1] = 0;
+    }
+    const cplx<R> *base = tile + (o0 * S01 + o1 * X2 + o2);
     R ar = 0, ai = 0;
-    for (int t0 = sub; t0 < Q2; t0 += S) {
-      const R w0 = gauss<R>(pr.frac[0] + (R)(q - 1 - t0), inv2lam);
-      const cplx<R> *plane = base + (size_t)t0 * X1 * X2;
+#pragma unroll
+    for (int j0 = 0; j0 < J; ++j0) {
+      const cplx<R> *plane = base + min(a + 4 * j0, Q2 - 1) * S01;
       R br = 0, bi = 0;
 #pragma unroll
-      for (int t1 = 0; t1 < Q2; ++t1) {
-        const cplx<R> *row = plane + t1 * X2;
+      for (int j1 = 0; j1 < J; ++j1) {
+        const cplx<R> *row = plane + min(b + 4 * j1, Q2 - 1) * X2;
         R cr = 0, ci = 0;
 #pragma unroll
         for (int t2 = 0; t2 < Q2; ++t2) {
@@ -137,17 +177,17 @@ __global__ __launch_bounds__(GatherTiled<Q2>::threads) void k_gather_tiled(const
           cr += w2[t2] * v.re;
           ci += w2[t2] * v.im;
         }
-        br += w1[t1] * cr;
-        bi += w1[t1] * ci;
+        br += w1[j1] * cr;
+        bi += w1[j1] * ci;
       }
-      ar += w0 * br;
-      ai += w0 * bi;
+      ar += w0[j0] * br;
+      ai += w0[j0] * bi;
     }
-    // (p0 + p1) + (p2 + p3) in every lane of the group
-    ar += __shfl_xor(ar, 1, 64);
-    ai += __shfl_xor(ai, 1, 64);
-    ar += __shfl_xor(ar, 2, 64);
-    ai += __shfl_xor(ai, 2, 64);
+#pragma unroll
+    for (int m = 1; m < kGatherLanes; m *= 2) {
+      ar += __shfl_xor(ar, m, 64);
+      ai += __shfl_xor(ai, m, 64);
+    }
     if (sub == 0) f[perm[k]] = cplx<R>{ar, ai};
   }
 }
@@ -1576,9 +1616,33 @@ __global__ __launch_bounds__(256) void k_ndft_adj(const cplx<R> *__restrict__ y,
   eta[e] = cplx<R>{(R)ar, (R)ai};
 }
 
+// Plane stride of the tiled gather's LDS box: the least S >= X1 X2 (and
+// within 16 of it) at which the rows a S + b X2, a, b < 4, that the sixteen
+// lanes of a point read together fall in 16 distinct value slots modulo 16,
+// and each half of them (a < 2, a >= 2) in 8 distinct slots modulo 8, so that
+// LDS passes of 16 lanes and of 8 lanes are both free of bank conflicts; X1 X2
+// itself where no such stride keeps the box within the LDS of a workgroup.
+int box_plane_stride(const Plan &p) {
+  const int base = p.X[1] * p.X[2];
+  const size_t cb = p.prec == SGL_F64 ? 16 : 8;
+  for (int s = base; s < base + 16; ++s) {
+    if ((size_t)p.X[0] * s * cb > (size_t)kLdsMax) break;
+    unsigned m16 = 0, m8[2] = {0, 0};
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 4; ++b) {
+        const int v = a * s + b * p.X[2];
+        m16 |= 1u << (v & 15);
+        m8[a / 2] |= 1u << (v & 7);
+      }
+    if (m16 == 0xffffu && m8[0] == 0xffu && m8[1] == 0xffu) return s;
+  }
+  return base;
+}
+
 Geom make_geom(const Plan &p) {
   Geom g;
   g.q = p.q;
+  g.S01 = box_plane_stride(p);
   for (int j = 0; j < 3; ++j) {
     g.N[j] = p.N[j];
     g.E[j] = p.E[j];
@@ -1608,7 +1672,7 @@ hipError_t gather_q(const Plan &p, const void *grid, void *f) {
     }
   }
   if (p.gather_mode == 0) {
-    const size_t lds = (size_t)p.X[0] * p.X[1] * p.X[2] * sizeof(cplx<R>);
+    const size_t lds = (size_t)p.X[0] * g.S01 * sizeof(cplx<R>);
     const bool narrow = p.gather_narrow || GatherTiled<Q2>::threads == 256;
     k_gather_tiled<R, Q2><<<(unsigned)p.nchunks, narrow ? 256 : GatherTiled<Q2>::threads, lds, p.stream>>>(
         (const cplx<R> *)grid, (const PointRec<R> *)p.pts, p.perm, p.chunks, g, inv2lam, (cplx<R> *)f);
