@@ -201,7 +201,8 @@ sgl_status setup_geometry(Plan &p) {
   }
   if ((uint64_t)p.ntiles * p.L[0] * p.L[1] * p.L[2] >= (1ull << 32)) return SGL_E_UNSUPPORTED;
   p.mfma = (p.prec == SGL_F32 && p.gather_mode == 0 && p.q <= 8 && p.L[0] == 8 && p.L[1] == 8 && p.L[2] == 8);
-  p.mfma64 = (p.prec == SGL_F64 && p.gather_mode == 0 && 7 + 2 * p.q <= 24 && p.L[0] == 8 && p.L[1] == 8 &&
+  // FP64 boxes of 8^3 tiles fit the LDS budget up to q = 6
+  p.mfma64 = (p.prec == SGL_F64 && p.gather_mode == 0 && p.q <= 6 && p.L[0] == 8 && p.L[1] == 8 &&
               p.L[2] == 8);
   // blocks of 16^3 stored cells of the cell-owned scatter (the last block of
   // a dimension may be partial)

@@ -897,19 +897,28 @@ __global__ __launch_bounds__(kSpread64Threads) void k_spread_mfma64(const cplx<d
     for (int ks = 0; ks < nb; ks += 4) {
       const int kr_lo = srb[ks / 4][0], kr_hi = srb[ks / 4][1], kc_hi = srb[ks / 4][2];
       const int pp = ks + kq;  // this lane's point of the K step (A column, B row)
-      double bf[NCB];
+      double bf[NCB], a[RBW];
 #pragma unroll
       for (int n = 0; n < NCB; ++n) bf[n] = bt[pp][16 * n + pl];
+      // A fragments of every owned row block, read whether or not the step
+      // needs the block, so that one wait covers all of the step's LDS reads
+      // (i0 clamped for blocks past the box, whose fragment goes unused)
+#pragma unroll
+      for (int r = 0; r < RBW; ++r) {
+        const int row = (wave + r * NW) * 16 + pl;
+        const int i0 = min(row / X, kTW64 - 1), i1 = row - (row / X) * X;
+        a[r] = tw[0][pp][i0] * tw[1][pp][i1];
+      }
+      // keeps the compiler from sinking the reads into the branch below
+#pragma unroll
+      for (int r = 0; r < RBW; ++r) __asm__ volatile("" ::"v"(a[r]));
 #pragma unroll
       for (int r = 0; r < RBW; ++r) {
         const int rb = wave + r * NW;
         if (rb < nrb && rb >= kr_lo && rb < kr_hi) {
-          const int row = rb * 16 + pl;
-          const int i0 = row / X, i1 = row - (row / X) * X;
-          const double a = tw[0][pp][i0] * tw[1][pp][i1];
 #pragma unroll
           for (int n = 0; n < NCB; ++n)
-            if (n < kc_hi) acc[r][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bf[n], acc[r][n], 0, 0, 0);
+            if (n < kc_hi) acc[r][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r], bf[n], acc[r][n], 0, 0, 0);
         }
       }
     }
@@ -1703,7 +1712,7 @@ hipError_t scatter_q(const Plan &p, const void *f, void *grid) {
       return hipGetLastError();
     }
   }
-  if constexpr (std::is_same<R, double>::value && Q2 <= 16) {
+  if constexpr (std::is_same<R, double>::value && Q2 <= 12) {
     if (p.mfma64) {
       k_spread_mfma64<Q2><<<(unsigned)p.nchunks, kSpread64Threads, 0, p.stream>>>(
           (const cplx<double> *)f, (const PointRec<double> *)p.pts, p.perm, p.chunks, g, (double)inv2lam,
