@@ -754,16 +754,23 @@ __host__ __device__ inline int bin_ranges(int S, int ext, int j, const Geom &g, 
 // c = re, im, on v_mfma_f64_16x16x4f64 with K = 4 points per step: A[row][p]
 // = w0 w1, B[p][col] with the real and imaginary parts interleaved along the
 // columns (col = 2 i2 + c, 2X columns in three blocks of 16 for X <= 24), so
-// every product is an exact FP64 multiply-add.  Per batch of kSB64 points the
-// workgroup stages the w0 and w1 tables and B in LDS; wave w owns the row
-// blocks w, w + 8, ... of the box for the whole chunk (accumulators in
-// registers) and skips, per K step, the row blocks outside
-// [min o0, max o0 + 2q) of its four points (A = 0 there).  The box goes to the
-// chunk's staging slot; the fold sums the boxes.  No atomics.
+// every product is an exact FP64 multiply-add.  The workgroup's waves split
+// into two roles over double-buffered LDS tables of kSB64 points: while
+// kSpread64Prod waves multiply batch b out of one buffer, the other waves load
+// batch b + 1 and build its w0 and w1 tables and B in the other buffer (one
+// thread per point and dimension; each thread clears the entries it wrote
+// into that buffer two batches before, so the tables are zero outside the
+// windows without a clearing pass), and one barrier per batch hands the
+// buffers over.  Product wave w owns the row blocks w, w + kSpread64Prod, ...
+// of the box for the whole chunk (accumulators in registers) and skips, per K
+// step, the row blocks outside [min o0, max o0 + 2q) and the column blocks
+// past 2 (max o2 + 2q) of its four points (A or B = 0 there).  The box goes
+// to the chunk's staging slot; the fold sums the boxes.  No atomics.
 constexpr int kSpread64Threads = 1024;  // 16 waves
-constexpr int kSB64 = 64;              // points staged at once
-constexpr int kTW64 = 33;              // doubles per w0/w1 table row (box index, padded)
-constexpr int kBT64 = 50;              // doubles per B row (48 columns, padded)
+constexpr int kSpread64Prod = 12;       // product waves; waves 12 .. 15 build tables
+constexpr int kSB64 = 64;               // points per batch
+constexpr int kTW64 = 33;               // doubles per w0/w1 table row (box index, padded)
+constexpr int kBT64 = 50;               // doubles per B row (48 columns, padded)
 
 template <int Q2>
 __global__ __launch_bounds__(kSpread64Threads) void k_spread_mfma64(const cplx<double> *__restrict__ y,
@@ -777,19 +784,17 @@ __global__ __launch_bounds__(kSpread64Threads) void k_spread_mfma64(const cplx<d
   constexpr int nrow = X * X;
   constexpr int nrb = (nrow + 15) / 16;
   constexpr int NCB = (2 * X + 15) / 16;
-  constexpr int NW = kSpread64Threads / 64;
+  constexpr int NW = kSpread64Prod;
   constexpr int RBW = (nrb + NW - 1) / NW;
   static_assert(X <= 24 && NCB <= 3, "box edge exceeds three column blocks");
   static_assert((nrb * 16 - 1) / X < 32, "row index past the weight tables");
-  // tw[d][p][i]: w_d of point p at box index i, d = 0, 1; zero outside the
-  // point's window, in particular for i >= X (rows past the box) and for the
-  // invalid points of a partial batch
-  __shared__ double tw[2][kSB64][kTW64];
-  __shared__ double bt[kSB64][kBT64];     // B[p][col], zero past 2X
-  __shared__ double sfr[3][kSB64];
-  __shared__ int so[3][kSB64];
-  __shared__ cplx<double> sy[kSB64];
-  __shared__ int srb[kSB64 / 4][3];       // row blocks a K step of 4 points meets, column blocks it needs
+  static_assert(kSpread64Threads - 64 * NW >= 3 * kSB64, "one builder thread per point and dimension");
+  // tw[buf][d][p][i]: w_d of point p at box index i, d = 0, 1; zero outside
+  // the point's window, in particular for i >= X (rows past the box) and for
+  // the invalid points of a partial batch.  bt[buf][p][col]: B, zero past 2X.
+  __shared__ double tw[2][2][kSB64][kTW64];
+  __shared__ double bt[2][kSB64][kBT64];
+  __shared__ int srb[2][kSB64 / 4][3];  // row blocks a K step of 4 points meets, column blocks it needs
 
   const int tidx = chunks[3 * blockIdx.x];
   const int start = chunks[3 * blockIdx.x + 1];
@@ -797,6 +802,97 @@ __global__ __launch_bounds__(kSpread64Threads) void k_spread_mfma64(const cplx<d
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int pl = lane & 15, kq = lane >> 4;
   const int c0 = tidx / (g.T[2] * g.T[1]), c1 = (tidx / g.T[2]) % g.T[1], c2 = tidx % g.T[2];
+  const int nbatch = (count + kSB64 - 1) / kSB64;
+
+  // both table buffers start at zero
+  for (int e = threadIdx.x; e < 2 * 2 * kSB64 * kTW64; e += kSpread64Threads) (&tw[0][0][0][0])[e] = 0.0;
+  for (int e = threadIdx.x; e < 2 * kSB64 * kBT64; e += kSpread64Threads) (&bt[0][0][0])[e] = 0.0;
+
+  // builder role: thread (bd, bp) handles dimension bd of point bp of a batch
+  const bool builder = wave >= NW;
+  const int tb = (int)threadIdx.x - 64 * NW;
+  const int bd = tb / kSB64, bp = tb % kSB64;  // bd = 3: idle
+  const int ct = bd == 0 ? c0 : (bd == 1 ? c1 : c2);
+  int oprev0 = -1, oprev1 = -1;  // window start this thread wrote into buffer 0 / 1 (-1: none)
+  // raw data of the thread's point of the next batch to build
+  bool nval = false;
+  double nfr = 0.0, nyre = 0.0, nyim = 0.0;
+  int ncell = 0;
+  auto fetch = [&](int b) {
+    nval = builder && bd < 3 && b < nbatch && b * kSB64 + bp < count;
+    if (nval) {
+      const int k = start + b * kSB64 + bp;
+      nfr = pts[k].frac[bd];
+      ncell = pts[k].cell;
+      if (bd == 2) {
+        const cplx<double> v = y[perm[k]];
+        nyre = v.re;
+        nyim = v.im;
+      }
+    }
+  };
+  // tables of batch b into buffer buf from the fetched data, then fetch b + 1
+  // (builder waves only; the thread's own entries, so no barrier inside)
+  auto build = [&](int b, int buf) {
+    const bool valid = nval;
+    const double fr = nfr, yre = nyre, yim = nyim;
+    const int cell = ncell;
+    fetch(b + 1);
+    if (bd >= 3) return;
+    const int o = valid ? (bd == 0 ? cell0(cell) : (bd == 1 ? cell1(cell) : cell2(cell))) - ct * 8 : -1;
+    const int op = buf ? oprev1 : oprev0;
+    if (op >= 0) {
+      for (int t = 0; t < Q2; ++t) {
+        if (bd < 2) {
+          tw[buf][bd][bp][op + t] = 0.0;
+        } else {
+          bt[buf][bp][2 * (op + t)] = 0.0;
+          bt[buf][bp][2 * (op + t) + 1] = 0.0;
+        }
+      }
+    }
+    if (valid) {
+      // window values by the Gaussian recurrence: with d_t = frac + q - 1 - t,
+      // w_{t+1} = w_t r_t, r_t = exp((2 d_t - 1) / (2 lambda)),
+      // r_{t+1} = r_t exp(-1 / lambda)
+      const double cc = exp(-2.0 * inv2lam);
+      const double d0 = fr + (double)(q - 1);
+      double w = exp(-d0 * d0 * inv2lam), r = exp((2.0 * d0 - 1.0) * inv2lam);
+      for (int t = 0; t < Q2; ++t) {
+        if (bd < 2) {
+          tw[buf][bd][bp][o + t] = w;
+        } else {
+          bt[buf][bp][2 * (o + t)] = yre * w;
+          bt[buf][bp][2 * (o + t) + 1] = yim * w;
+        }
+        w *= r;
+        r *= cc;
+      }
+    }
+    if (buf) oprev1 = o; else oprev0 = o;
+    // row blocks of a K step: rows i0 * X + i1 with i0 outside
+    // [min o0, max o0 + Q2) of its points have A = 0, so the step only needs
+    // the row blocks that meet that range; columns 2 i2 + c with i2 at or past
+    // max o2 + Q2 have B = 0, so it only needs the column blocks below
+    // 2 (max o2 + Q2).  Groups of four lanes of the dimension-0 and dimension-2
+    // waves hold the four points of a step.
+    if (bd == 0) {
+      int lo = valid ? o : X, hi = valid ? o : 0;
+      lo = min(lo, __shfl_xor(lo, 1, 64));
+      hi = max(hi, __shfl_xor(hi, 1, 64));
+      lo = min(lo, __shfl_xor(lo, 2, 64));
+      hi = max(hi, __shfl_xor(hi, 2, 64));
+      if ((bp & 3) == 0) {
+        srb[buf][bp / 4][0] = lo < X ? (lo * X) / 16 : nrb;
+        srb[buf][bp / 4][1] = lo < X ? min(nrb, ((hi + Q2) * X + 15) / 16) : nrb;
+      }
+    } else if (bd == 2) {
+      int hi2 = valid ? o : 0;
+      hi2 = max(hi2, __shfl_xor(hi2, 1, 64));
+      hi2 = max(hi2, __shfl_xor(hi2, 2, 64));
+      if ((bp & 3) == 0) srb[buf][bp / 4][2] = min(NCB, (2 * min(X, hi2 + Q2) + 15) / 16);
+    }
+  };
 
   sgl_double4 acc[RBW][NCB];
 #pragma unroll
@@ -804,126 +900,49 @@ __global__ __launch_bounds__(kSpread64Threads) void k_spread_mfma64(const cplx<d
 #pragma unroll
     for (int n = 0; n < NCB; ++n) acc[r][n] = sgl_double4{0.0, 0.0, 0.0, 0.0};
 
-  // the next batch's point data, one value per thread (threads 0 .. 6 kSB64 - 1:
-  // field f = t / kSB64 of point t % kSB64: fractions 0..2, base cell, sample
-  // re, im), loaded while the current batch is multiplied
-  const int pf = threadIdx.x % kSB64, ff = threadIdx.x / kSB64;
-  double nv = 0.0;
-  int ncell = 0;
-  auto fetch = [&](int b0n) {
-    if (ff < 6 && b0n + pf < count) {
-      const int k = start + b0n + pf;
-      if (ff < 3) {
-        nv = pts[k].frac[ff];
-      } else if (ff == 3) {
-        ncell = pts[k].cell;
-      } else {
-        const cplx<double> v = y[perm[k]];
-        nv = ff == 4 ? v.re : v.im;
-      }
-    }
-  };
   fetch(0);
-
-  for (int b0 = 0; b0 < count; b0 += kSB64) {
-    const int nb = min(kSB64, count - b0);
-    // 1. the batch's point records and samples (fetched during the last batch)
-    if (ff < 6) {
-      const bool valid = pf < nb;
-      if (ff < 3) {
-        sfr[ff][pf] = valid ? nv : 0.0;
-      } else if (ff == 3) {
-        // offsets in [0, 8): the point lies in this tile; far outside every box when invalid
-        so[0][pf] = valid ? cell0(ncell) - c0 * 8 : 1 << 20;
-        so[1][pf] = valid ? cell1(ncell) - c1 * 8 : 1 << 20;
-        so[2][pf] = valid ? cell2(ncell) - c2 * 8 : 1 << 20;
-      } else if (ff == 4) {
-        sy[pf].re = valid ? nv : 0.0;
-      } else {
-        sy[pf].im = valid ? nv : 0.0;
-      }
-    }
-    __syncthreads();
-    // 2. zero tables, then per point and dimension its 2q window values by the
-    //    Gaussian recurrence: with d_t = frac + q - 1 - t, w_{t+1} = w_t r_t,
-    //    r_t = exp((2 d_t - 1) / (2 lambda)), r_{t+1} = r_t exp(-1 / lambda)
-    //    (dimensions 0 and 1 into the weight tables, dimension 2 times the
-    //    sample into B)
-    for (int e = threadIdx.x; e < 2 * kSB64 * kTW64; e += kSpread64Threads) (&tw[0][0][0])[e] = 0.0;
-    for (int e = threadIdx.x; e < kSB64 * kBT64; e += kSpread64Threads) (&bt[0][0])[e] = 0.0;
-    __syncthreads();
-    if ((int)threadIdx.x < 3 * kSB64) {
-      const int d = threadIdx.x / kSB64, pp = threadIdx.x % kSB64;
-      if (pp < nb) {
-        const double cc = exp(-2.0 * inv2lam);
-        const double d0 = sfr[d][pp] + (double)(q - 1);
-        double w = exp(-d0 * d0 * inv2lam), r = exp((2.0 * d0 - 1.0) * inv2lam);
-        const int o = so[d][pp];
-        const cplx<double> yv = sy[pp];
-        for (int t = 0; t < Q2; ++t) {
-          if (d < 2) {
-            tw[d][pp][o + t] = w;
-          } else {
-            bt[pp][2 * (o + t)] = yv.re * w;
-            bt[pp][2 * (o + t) + 1] = yv.im * w;
+  __syncthreads();  // tables zeroed
+  if (builder) build(0, 0);
+  __syncthreads();
+  for (int b = 0; b < nbatch; ++b) {
+    const int buf = b & 1;
+    if (!builder) {
+      const int nb = min(kSB64, count - b * kSB64);
+      // products over the batch, K = 4 points per step
+      for (int ks = 0; ks < nb; ks += 4) {
+        const int kr_lo = srb[buf][ks / 4][0], kr_hi = srb[buf][ks / 4][1], kc_hi = srb[buf][ks / 4][2];
+        const int pp = ks + kq;  // this lane's point of the K step (A column, B row)
+        double bf[NCB], a[RBW];
+#pragma unroll
+        for (int n = 0; n < NCB; ++n) bf[n] = bt[buf][pp][16 * n + pl];
+        // A fragments of every owned row block, read whether or not the step
+        // needs the block, so that one wait covers all of the step's LDS reads
+        // (i0 clamped for blocks past the box, whose fragment goes unused)
+#pragma unroll
+        for (int r = 0; r < RBW; ++r) {
+          const int row = (wave + r * NW) * 16 + pl;
+          const int i0 = min(row / X, kTW64 - 1), i1 = row - (row / X) * X;
+          a[r] = tw[buf][0][pp][i0] * tw[buf][1][pp][i1];
+        }
+        // keeps the compiler from sinking the reads into the branch below
+#pragma unroll
+        for (int r = 0; r < RBW; ++r) __asm__ volatile("" ::"v"(a[r]));
+#pragma unroll
+        for (int r = 0; r < RBW; ++r) {
+          const int rb = wave + r * NW;
+          if (rb < nrb && rb >= kr_lo && rb < kr_hi) {
+#pragma unroll
+            for (int n = 0; n < NCB; ++n)
+              if (n < kc_hi) acc[r][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r], bf[n], acc[r][n], 0, 0, 0);
           }
-          w *= r;
-          r *= cc;
         }
       }
+    } else if (b + 1 < nbatch) {
+      build(b + 1, buf ^ 1);
     }
-    if ((int)threadIdx.x < kSB64 / 4) {
-      // rows i0 * X + i1 with i0 outside [min o0, max o0 + Q2) of a K step's
-      // points have A = 0 there, so the step only needs the row blocks that
-      // meet that range; columns 2 i2 + c with i2 at or past max o2 + Q2 have
-      // B = 0, so it only needs the column blocks below 2 (max o2 + Q2)
-      const int k4 = threadIdx.x;
-      int lo = X, hi = 0, hi2 = 0;
-      for (int j = 0; j < 4; ++j) {
-        const int pp = 4 * k4 + j;
-        if (pp < nb) {
-          lo = min(lo, so[0][pp]);
-          hi = max(hi, so[0][pp]);
-          hi2 = max(hi2, so[2][pp]);
-        }
-      }
-      srb[k4][0] = lo < X ? (lo * X) / 16 : nrb;
-      srb[k4][1] = lo < X ? min(nrb, ((hi + Q2) * X + 15) / 16) : nrb;
-      srb[k4][2] = min(NCB, (2 * min(X, hi2 + Q2) + 15) / 16);
-    }
-    __syncthreads();
-    if (b0 + kSB64 < count) fetch(b0 + kSB64);
-    // 3. products over the batch, K = 4 points per step
-    for (int ks = 0; ks < nb; ks += 4) {
-      const int kr_lo = srb[ks / 4][0], kr_hi = srb[ks / 4][1], kc_hi = srb[ks / 4][2];
-      const int pp = ks + kq;  // this lane's point of the K step (A column, B row)
-      double bf[NCB], a[RBW];
-#pragma unroll
-      for (int n = 0; n < NCB; ++n) bf[n] = bt[pp][16 * n + pl];
-      // A fragments of every owned row block, read whether or not the step
-      // needs the block, so that one wait covers all of the step's LDS reads
-      // (i0 clamped for blocks past the box, whose fragment goes unused)
-#pragma unroll
-      for (int r = 0; r < RBW; ++r) {
-        const int row = (wave + r * NW) * 16 + pl;
-        const int i0 = min(row / X, kTW64 - 1), i1 = row - (row / X) * X;
-        a[r] = tw[0][pp][i0] * tw[1][pp][i1];
-      }
-      // keeps the compiler from sinking the reads into the branch below
-#pragma unroll
-      for (int r = 0; r < RBW; ++r) __asm__ volatile("" ::"v"(a[r]));
-#pragma unroll
-      for (int r = 0; r < RBW; ++r) {
-        const int rb = wave + r * NW;
-        if (rb < nrb && rb >= kr_lo && rb < kr_hi) {
-#pragma unroll
-          for (int n = 0; n < NCB; ++n)
-            if (n < kc_hi) acc[r][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r], bf[n], acc[r][n], 0, 0, 0);
-        }
-      }
-    }
-    __syncthreads();  // the batch's tables are consumed
+    __syncthreads();  // batch b consumed, batch b + 1 built
   }
+  if (builder) return;
   // D[kq + 4v][pl] of every (row block, column block) to the chunk's box
   double *out = (double *)(staging + (size_t)blockIdx.x * nrow * X);
 #pragma unroll
