@@ -51,7 +51,8 @@ __device__ inline int stored_index(int l, int j, const Geom &g) {
     const int s = l - g.lo[j];
     return (s >= 0 && s < g.E[j]) ? s : -1;
   }
-  int s = l % g.N[j];
+  if (l >= 0 && l < g.N[j]) return l;
+  const int s = l % g.N[j];
   return s < 0 ? s + g.N[j] : s;
 }
 
@@ -77,30 +78,32 @@ __device__ inline R gauss(R d, R inv2lam) {
 // sixteen distinct groups of four banks (a value is 16 bytes in FP64).  The
 // gather is bound by LDS bandwidth, and rows of different points meeting in a
 // pass cost it a quarter more in bank conflicts.
+// The window values of a point are computed once, by its sixteen lanes (at
+// most three exponentials each), into an LDS slot of the point that all
+// sixteen lanes then read; the box fill divides by the box edges in single
+// precision, which is exact here.
 // 1,024-thread workgroups run 16 waves per CU; the narrow form (256 threads)
 // leaves registers for a scatter running beside it on the same CU, with the
 // same sums and so the same bits.
 template <int Q2>
 struct GatherTiled {
   static constexpr int threads = Q2 <= 12 ? 1024 : Q2 <= 16 ? 512 : 256;
+  static constexpr int J = (Q2 + 3) / 4;  // rows per lane along dimensions 0 and 1
+  // values of a point slot: w2 at t = 0 .. Q2 - 1, then w0 and w1 at the
+  // rows a + 4 j (b + 4 j) of the four lanes a (b), j < J
+  static constexpr int nwv = Q2 + 8 * J;
+  // slot stride: 16 modulo 32 values, so that the two points of a 32-lane
+  // pass of 8-byte reads meet opposite halves of the banks
+  static constexpr int ws = nwv <= 16 ? 16 : (nwv + 15) / 32 * 32 + 16;
+  template <class R>
+  static constexpr size_t slot_bytes(int nthreads) {
+    return (size_t)(nthreads / 16) * ws * sizeof(R);
+  }
 };
 constexpr int kGatherLanes = 16;
-
-// Gaussian window values exp(-u_j^2 / (2 lambda)) at u_j = u - s j for
-// j < n, by the recurrence w_(j+1) = w_j r_j, r_j = exp((2 s u_j - s^2) /
-// (2 lambda)), r_(j+1) = r_j exp(-2 s^2 / (2 lambda)): two exponentials in
-// place of n (FP64; the relative error grows by about one rounding per step).
-template <int n, int s>
-__device__ inline void gauss_run(double u, double inv2lam, double cs, double *w) {
-  double wv = exp(-u * u * inv2lam);
-  double r = exp((2.0 * s * u - (double)(s * s)) * inv2lam);
-#pragma unroll
-  for (int j = 0; j < n; ++j) {
-    w[j] = wv;
-    wv *= r;
-    r *= cs;
-  }
-}
+// largest box the tiled gather takes: the fill's single-precision division is
+// exact for element indices below 2^14
+constexpr int kGatherBoxMax = 1 << 14;
 
 template <class R, int Q2>
 __global__ __launch_bounds__(GatherTiled<Q2>::threads) void k_gather_tiled(const cplx<R> *__restrict__ grid,
@@ -109,9 +112,8 @@ __global__ __launch_bounds__(GatherTiled<Q2>::threads) void k_gather_tiled(const
                                                       const int32_t *__restrict__ chunks, Geom g, R inv2lam,
                                                       cplx<R> *__restrict__ f) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  cplx<R> *tile = (cplx<R> *)smem;
   constexpr int q = Q2 / 2;
-  constexpr int J = (Q2 + 3) / 4;  // rows per lane along dimensions 0 and 1
+  constexpr int J = GatherTiled<Q2>::J, NWV = GatherTiled<Q2>::nwv, WS = GatherTiled<Q2>::ws;
   const int tidx = chunks[3 * blockIdx.x];
   const int start = chunks[3 * blockIdx.x + 1];
   const int count = chunks[3 * blockIdx.x + 2];
@@ -119,9 +121,15 @@ __global__ __launch_bounds__(GatherTiled<Q2>::threads) void k_gather_tiled(const
   const int c1 = (tidx / g.T[2]) % g.T[1];
   const int c0 = tidx / (g.T[2] * g.T[1]);
   const int X0 = g.X[0], X1 = g.X[1], X2 = g.X[2], S01 = g.S01;
+  cplx<R> *tile = (cplx<R> *)smem;
+  R *wslots = (R *)(smem + (size_t)X0 * S01 * sizeof(cplx<R>));
   const int wb0 = c0 * g.L[0] - q + 1, wb1 = c1 * g.L[1] - q + 1, wb2 = c2 * g.L[2] - q + 1;
+  // e = (i0 X1 + i1) X2 + i2 < 2^14: (e + 1/2) / X2 lies at least 1 / (2 X2)
+  // from an integer, and the single-precision product is within 2^-10 of it
+  const float rX2 = 1.0f / (float)X2, rX1 = 1.0f / (float)X1;
   for (int e = threadIdx.x; e < X0 * X1 * X2; e += blockDim.x) {
-    const int i2 = e % X2, r = e / X2, i1 = r % X1, i0 = r / X1;
+    const int r = (int)(((float)e + 0.5f) * rX2), i2 = e - r * X2;
+    const int i0 = (int)(((float)r + 0.5f) * rX1), i1 = r - i0 * X1;
     const int s0 = stored_index(wb0 + i0, 0, g), s1 = stored_index(wb1 + i1, 1, g),
               s2 = stored_index(wb2 + i2, 2, g);
     // two scalars rather than a conditionally assigned pair, which the
@@ -141,40 +149,55 @@ __global__ __launch_bounds__(GatherTiled<Q2>::threads) void k_gather_tiled(const
   // sixteen lanes of a point share k, so they are active or inactive together
   // around the exchanges, which stay inside the group (lane xor 1, 2, 12, 20).
   const int lane = threadIdx.x % 64, qd = (lane % 32) / 4;
-  const int a = qd >> 1, b = lane % 4;
+  const int a = qd >> 1, b = lane % 4, sub = 4 * a + b;
   const int slot = ((int)threadIdx.x / 64) * 4 + (lane / 32) * 2 + (__popc(qd) & 1);
   const bool lead = (lane % 32) == (__popc(qd) & 1) * 4;  // a = 0, b = 0
-  const R cs1 = exp((R)-2 * inv2lam), cs4 = exp((R)-32 * inv2lam);
+  R *ws = wslots + slot * WS;
   for (int k = start + slot; k < start + count; k += (int)blockDim.x / kGatherLanes) {
     const PointRec<R> pr = pts[k];
     const int o0 = cell0(pr.cell) - c0 * g.L[0];
     const int o1 = cell1(pr.cell) - c1 * g.L[1];
     const int o2 = cell2(pr.cell) - c2 * g.L[2];
-    // w0[j] at t0 = a + 4 j, w1[j] at t1 = b + 4 j (zero past the window),
-    // w2[t] at t2 = t; the window value at offset t is gauss(frac + q - 1 - t)
-    R w0[J], w1[J], w2[Q2];
-    if constexpr (std::is_same<R, double>::value) {
-      gauss_run<J, 4>(pr.frac[0] + (double)(q - 1 - a), inv2lam, cs4, w0);
-      gauss_run<J, 4>(pr.frac[1] + (double)(q - 1 - b), inv2lam, cs4, w1);
-      gauss_run<Q2, 1>(pr.frac[2] + (double)(q - 1), inv2lam, cs1, w2);
-    } else {
+    // the point's window values into its slot, value v by lane v % 16: the
+    // value at window offset t is gauss(frac + q - 1 - t), zero past the
+    // window (rows a + 4 j >= Q2 of the last j)
 #pragma unroll
-      for (int j = 0; j < J; ++j) {
-        w0[j] = gauss<R>(pr.frac[0] + (R)(q - 1 - a - 4 * j), inv2lam);
-        w1[j] = gauss<R>(pr.frac[1] + (R)(q - 1 - b - 4 * j), inv2lam);
+    for (int m = 0; m < (NWV + 15) / 16; ++m) {
+      const int v = sub + 16 * m;
+      if (v < NWV) {
+        int t;
+        R fr;
+        if (v < Q2) {
+          t = v;
+          fr = pr.frac[2];
+        } else if (v < Q2 + 4 * J) {
+          t = (v - Q2) / J + 4 * ((v - Q2) % J);
+          fr = pr.frac[0];
+        } else {
+          t = (v - Q2 - 4 * J) / J + 4 * ((v - Q2 - 4 * J) % J);
+          fr = pr.frac[1];
+        }
+        ws[v] = t < Q2 ? gauss<R>(fr + (R)(q - 1 - t), inv2lam) : (R)0;
       }
-#pragma unroll
-      for (int t = 0; t < Q2; ++t) w2[t] = gauss<R>(pr.frac[2] + (R)(q - 1 - t), inv2lam);
     }
-    if constexpr (Q2 % 4 != 0) {
-      // rows past the window read its last row (inside the box) with weight 0
-      if (a + 4 * (J - 1) >= Q2) w0[J - 1] = 0;
-      if (b + 4 * (J - 1) >= Q2) w1[J - 1] = 0;
+    // the slot's writers and readers are lanes of this wave: LDS operations
+    // of a wave complete in order, the fences keep the compiler's order
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    R w0[J], w1[J], w2[Q2];
+#pragma unroll
+    for (int t = 0; t < Q2; ++t) w2[t] = ws[t];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      w0[j] = ws[Q2 + a * J + j];
+      w1[j] = ws[Q2 + 4 * J + b * J + j];
     }
     const cplx<R> *base = tile + (o0 * S01 + o1 * X2 + o2);
     R ar = 0, ai = 0;
 #pragma unroll
     for (int j0 = 0; j0 < J; ++j0) {
+      // rows past the window read its last row (inside the box) with weight 0
       const cplx<R> *plane = base + min(a + 4 * j0, Q2 - 1) * S01;
       R br = 0, bi = 0;
 #pragma unroll
@@ -201,6 +224,10 @@ __global__ __launch_bounds__(GatherTiled<Q2>::threads) void k_gather_tiled(const
       ai += __shfl_xor(ai, kXor[m], 64);
     }
     if (lead) f[perm[k]] = cplx<R>{ar, ai};
+    // the slot is read before the next point's values overwrite it
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 }
 
@@ -1665,7 +1692,8 @@ int box_plane_stride(const Plan &p) {
   const int base = p.X[1] * p.X[2];
   const size_t cb = p.prec == SGL_F64 ? 16 : 8;
   for (int s = base; s < base + 16; ++s) {
-    if ((size_t)p.X[0] * s * cb > (size_t)kLdsMax) break;
+    // room for the point slots of a 1,024-thread workgroup (48 values each)
+    if ((size_t)p.X[0] * s * cb + 64 * 48 * cb / 2 > (size_t)kLdsMax) break;
     unsigned m16 = 0;
     for (int a = 0; a < 4; ++a)
       for (int b = 0; b < 4; ++b) m16 |= 1u << ((a * s + b * p.X[2]) & 15);
@@ -1707,9 +1735,12 @@ hipError_t gather_q(const Plan &p, const void *grid, void *f) {
     }
   }
   if (p.gather_mode == 0) {
-    const size_t lds = (size_t)p.X[0] * g.S01 * sizeof(cplx<R>);
+    if (p.X[0] * p.X[1] * p.X[2] >= kGatherBoxMax) return hipErrorInvalidValue;
     const bool narrow = p.gather_narrow || GatherTiled<Q2>::threads == 256;
-    k_gather_tiled<R, Q2><<<(unsigned)p.nchunks, narrow ? 256 : GatherTiled<Q2>::threads, lds, p.stream>>>(
+    const int nthreads = narrow ? 256 : GatherTiled<Q2>::threads;
+    const size_t lds =
+        (size_t)p.X[0] * g.S01 * sizeof(cplx<R>) + GatherTiled<Q2>::template slot_bytes<R>(nthreads);
+    k_gather_tiled<R, Q2><<<(unsigned)p.nchunks, nthreads, lds, p.stream>>>(
         (const cplx<R> *)grid, (const PointRec<R> *)p.pts, p.perm, p.chunks, g, inv2lam, (cplx<R> *)f);
   } else {
     const size_t lds = (size_t)kSlab * p.X[1] * p.X[2] * sizeof(cplx<R>);
