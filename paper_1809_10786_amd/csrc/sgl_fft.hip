@@ -247,14 +247,19 @@ constexpr int p2_stride() {
   return STRIDED ? W : W + 1;
 }
 
-// Lines per workgroup for length L = 2^LOG2L and element type R: as many as
-// keep the line buffer and the twiddles within 78 KB (two workgroups per
-// compute unit), at most 16 (16 FP32 or 8 FP64 lines fill a 128-byte row of a
-// strided pass).
+// Lines per workgroup for length L = 2^LOG2L and element type R.  A strided
+// pass reads every row of its lines as one segment of W adjacent values, so
+// it takes 8 lines (a 128-byte segment of FP64 values) within 78 KB of line
+// buffer and twiddles (two workgroups per compute unit).  A contiguous pass
+// reads whole lines, so it takes as many as fit 39 KB, which leaves room for
+// four workgroups per compute unit whose loads, transforms and stores
+// overlap (measured on the B = 64 FP64 passes: the contiguous ones moved
+// 2.7-3.2 TB/s with 16 lines and 4.3 TB/s with 4).
 template <class R, int LOG2L, bool STRIDED>
 constexpr int p2_lines() {
-  int w = 16;
-  while (w > 1 && ((size_t)(1 << LOG2L) * (STRIDED ? w : w + 1) + (1 << LOG2L)) * sizeof(cplx<R>) > 78 * 1024)
+  int w = STRIDED ? 128 / (int)sizeof(cplx<R>) : 16;
+  const size_t budget = (STRIDED ? 78 : 39) * 1024;
+  while (w > 1 && ((size_t)(1 << LOG2L) * (STRIDED ? w : w + 1) + (1 << LOG2L)) * sizeof(cplx<R>) > budget)
     w /= 2;
   return w;
 }
