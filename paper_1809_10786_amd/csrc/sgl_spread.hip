@@ -44,6 +44,7 @@ struct Geom {
   int L[3], T[3], X[3], NB[3];
   int Lo[3], To[3];
   int S01;  // plane stride of the tiled gather's LDS box, >= X1 X2
+  int SR;   // row stride of the slab gather's LDS slabs, >= X2
 };
 
 __device__ inline int stored_index(int l, int j, const Geom &g) {
@@ -520,12 +521,32 @@ __global__ __launch_bounds__(GatherShape<Q2>::threads) void k_gather_mfma(const 
 
 // Gather for windows too wide for the whole box of a tile in LDS (large q):
 // one workgroup per chunk streams the box through LDS in slabs of kSlab
-// dimension-0 planes.  The chunk's points are taken 64 at a time, four
-// adjacent lanes per point, lane `sub` summing the rows t1 = sub, sub + 4, ...
-// of every plane of the point's window; the partial sums stay in registers
-// across the slabs and the four lanes add them as (p0 + p1) + (p2 + p3).
+// dimension-0 planes.  The chunk's points are taken 64 at a time, sixteen
+// lanes per point in one LDS pass group (as in the tiled gather): lane
+// (r, h), r < 8, h < 2, sums the rows t1 = r + 8 m of every plane of the
+// point's window that the slab holds, over the taps t2 = 2 j + h.  Slab rows
+// lie SR values apart with SR = 2 (mod 4), chosen on the host, so the sixteen
+// values read together (r SR + h) fall in sixteen distinct groups of banks,
+// and a lane keeps only its half of the point's dimension-2 window in
+// registers.  The point's window values along all three dimensions are
+// computed once per point, by its sixteen lanes, into an LDS slot; the
+// partial sums stay in registers across the slabs and the sixteen lanes add
+// them in a fixed butterfly.
 constexpr int kSlab = 4;
-constexpr int kSlabThreads = 256;
+constexpr int kSlabThreads = 1024;
+template <int Q2>
+struct GatherSlab {
+  static constexpr int M = (Q2 + 7) / 8;  // rows per lane and plane
+  static constexpr int H = Q2 / 2;        // taps per lane and row
+  // slot: w0 and w1 at window offsets 0 .. Q2 - 1, then w2 at the even and
+  // at the odd offsets; stride 16 modulo 32 values
+  static constexpr int nwv = 3 * Q2;
+  static constexpr int ws = nwv <= 16 ? 16 : (nwv + 15) / 32 * 32 + 16;
+  template <class R>
+  static constexpr size_t slot_bytes() {
+    return (size_t)(kSlabThreads / 16) * ws * sizeof(R);
+  }
+};
 
 template <class R, int Q2>
 __global__ __launch_bounds__(kSlabThreads) void k_gather_slab(const cplx<R> *__restrict__ grid,
@@ -534,20 +555,29 @@ __global__ __launch_bounds__(kSlabThreads) void k_gather_slab(const cplx<R> *__r
                                                               const int32_t *__restrict__ chunks, Geom g,
                                                               R inv2lam, cplx<R> *__restrict__ f) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  cplx<R> *slab = (cplx<R> *)smem;  // [kSlab][X1][X2]
   constexpr int q = Q2 / 2;
-  constexpr int T1 = (Q2 + 3) / 4;  // rows per lane
+  constexpr int M = GatherSlab<Q2>::M, H = GatherSlab<Q2>::H;
+  constexpr int NWV = GatherSlab<Q2>::nwv, WS = GatherSlab<Q2>::ws;
   const int tidx = chunks[3 * blockIdx.x];
   const int start = chunks[3 * blockIdx.x + 1];
   const int count = chunks[3 * blockIdx.x + 2];
   const int c2 = tidx % g.T[2];
   const int c1 = (tidx / g.T[2]) % g.T[1];
   const int c0 = tidx / (g.T[2] * g.T[1]);
-  const int X0 = g.X[0], X1 = g.X[1], X2 = g.X[2];
+  const int X0 = g.X[0], X1 = g.X[1], X2 = g.X[2], SR = g.SR;
+  cplx<R> *slab = (cplx<R> *)smem;  // [kSlab][X1][SR]
+  R *wslots = (R *)(smem + (size_t)kSlab * X1 * SR * sizeof(cplx<R>));
   const int wb0 = c0 * g.L[0] - q + 1, wb1 = c1 * g.L[1] - q + 1, wb2 = c2 * g.L[2] - q + 1;
-  const int sub = threadIdx.x & 3;
-  for (int pass = 0; pass < count; pass += kSlabThreads / 4) {
-    const int idx = pass + (int)threadIdx.x / 4;
+  // lane -> (point slot, sub) by LDS pass group, as in the tiled gather
+  const int lane = threadIdx.x % 64, qd = (lane % 32) / 4;
+  const int sub = 4 * (qd >> 1) + lane % 4, rr = sub >> 1, hh = sub & 1;
+  const int slot = ((int)threadIdx.x / 64) * 4 + (lane / 32) * 2 + (__popc(qd) & 1);
+  const bool lead = (lane % 32) == (__popc(qd) & 1) * 4;  // sub = 0
+  R *ws = wslots + slot * WS;
+  // slab element e = (ip X1 + i1) X2 + i2 < 2^14: exact single-precision division
+  const float rX2 = 1.0f / (float)X2, rX1 = 1.0f / (float)X1;
+  for (int pass = 0; pass < count; pass += kSlabThreads / 16) {
+    const int idx = pass + slot;
     const bool valid = idx < count;
     PointRec<R> pr;
     pr.frac[0] = pr.frac[1] = pr.frac[2] = 0;
@@ -559,20 +589,35 @@ __global__ __launch_bounds__(kSlabThreads) void k_gather_slab(const cplx<R> *__r
       o1 = cell1(pr.cell) - c1 * g.L[1];
       o2 = cell2(pr.cell) - c2 * g.L[2];
     }
-    R w1[T1], w2[Q2];
+    // the point's window values, value v by lane v % 16: v = d Q2 + t for
+    // d = 0, 1; w2 at offset t in 2 Q2 + (t % 2) H + t / 2
 #pragma unroll
-    for (int t = 0; t < T1; ++t) {
-      const int t1 = sub + 4 * t;
-      w1[t] = t1 < Q2 ? gauss<R>(pr.frac[1] + (R)(q - 1 - t1), inv2lam) : (R)0;
+    for (int m = 0; m < (NWV + 15) / 16; ++m) {
+      const int v = sub + 16 * m;
+      if (v < NWV) {
+        const int d = v / Q2, u = v - d * Q2;
+        const int t = d < 2 ? u : (u < H ? 2 * u : 2 * (u - H) + 1);
+        const R fr = d == 0 ? pr.frac[0] : (d == 1 ? pr.frac[1] : pr.frac[2]);
+        ws[v] = gauss<R>(fr + (R)(q - 1 - t), inv2lam);
+      }
     }
+    // writers and readers of the slot are lanes of this wave
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    R w2[H], w1[M];
 #pragma unroll
-    for (int t = 0; t < Q2; ++t) w2[t] = gauss<R>(pr.frac[2] + (R)(q - 1 - t), inv2lam);
+    for (int j = 0; j < H; ++j) w2[j] = ws[2 * Q2 + hh * H + j];
+    // rows past the window read its last row (inside the box) with weight 0
+#pragma unroll
+    for (int m = 0; m < M; ++m) w1[m] = rr + 8 * m < Q2 ? ws[Q2 + rr + 8 * m] : (R)0;
     R ar = 0, ai = 0;
     for (int s0 = 0; s0 < X0; s0 += kSlab) {
       const int np = min(kSlab, X0 - s0);
       __syncthreads();  // the previous slab is consumed
       for (int e = threadIdx.x; e < np * X1 * X2; e += kSlabThreads) {
-        const int i2 = e % X2, r = e / X2, i1 = r % X1, ip = r / X1;
+        const int r = (int)(((float)e + 0.5f) * rX2), i2 = e - r * X2;
+        const int ip = (int)(((float)r + 0.5f) * rX1), i1 = r - ip * X1;
         const int sa = stored_index(wb0 + s0 + ip, 0, g), sb = stored_index(wb1 + i1, 1, g),
                   sc = stored_index(wb2 + i2, 2, g);
         R vr = 0, vi = 0;
@@ -581,41 +626,47 @@ __global__ __launch_bounds__(kSlabThreads) void k_gather_slab(const cplx<R> *__r
           vr = v.re;
           vi = v.im;
         }
-        slab[e] = cplx<R>{vr, vi};
+        slab[r * SR + i2] = cplx<R>{vr, vi};
       }
       __syncthreads();
       // planes of this slab inside the point's window
       const int p_lo = max(s0, o0), p_hi = min(s0 + np, o0 + Q2);
       for (int i0 = p_lo; i0 < p_hi; ++i0) {
-        const R w0 = gauss<R>(pr.frac[0] + (R)(q - 1 - (i0 - o0)), inv2lam);
-        const cplx<R> *plane = slab + (size_t)(i0 - s0) * X1 * X2 + o2;
+        const R w0 = ws[i0 - o0];
+        const cplx<R> *plane = slab + (size_t)(i0 - s0) * X1 * SR + o2 + hh;
         R br = 0, bi = 0;
 #pragma unroll
-        for (int t = 0; t < T1; ++t) {
-          const int t1 = sub + 4 * t;
-          if (t1 < Q2) {
-            const cplx<R> *row = plane + (size_t)(o1 + t1) * X2;
-            R cr = 0, ci = 0;
+        for (int m = 0; m < M; ++m) {
+          const cplx<R> *row = plane + (size_t)(o1 + min(rr + 8 * m, Q2 - 1)) * SR;
+          R cr = 0, ci = 0;
 #pragma unroll
-            for (int t2 = 0; t2 < Q2; ++t2) {
-              const cplx<R> v = row[t2];
-              cr += w2[t2] * v.re;
-              ci += w2[t2] * v.im;
-            }
-            br += w1[t] * cr;
-            bi += w1[t] * ci;
+          for (int j = 0; j < H; ++j) {
+            const cplx<R> v = row[2 * j];
+            cr += w2[j] * v.re;
+            ci += w2[j] * v.im;
+            if (j % 4 == 3) __builtin_amdgcn_sched_barrier(0);
           }
+          br += w1[m] * cr;
+          bi += w1[m] * ci;
+          // bounds how far the scheduler hoists the row reads (registers)
+          __builtin_amdgcn_sched_barrier(0);
         }
         ar += w0 * br;
         ai += w0 * bi;
       }
     }
-    // (p0 + p1) + (p2 + p3) in every lane of the group
-    ar += __shfl_xor(ar, 1, 64);
-    ai += __shfl_xor(ai, 1, 64);
-    ar += __shfl_xor(ar, 2, 64);
-    ai += __shfl_xor(ai, 2, 64);
-    if (valid && sub == 0) f[perm[start + idx]] = cplx<R>{ar, ai};
+    // butterfly over the group: every lane ends with the same sum
+    constexpr int kXor[4] = {1, 2, 12, 20};
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      ar += __shfl_xor(ar, kXor[m], 64);
+      ai += __shfl_xor(ai, kXor[m], 64);
+    }
+    if (valid && lead) f[perm[start + idx]] = cplx<R>{ar, ai};
+    // the slot is read before the next pass's values overwrite it
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 }
 
@@ -1702,10 +1753,22 @@ int box_plane_stride(const Plan &p) {
   return base;
 }
 
+// Row stride of the slab gather's LDS slabs: the least S >= X2 with S = 2
+// (mod 4), so that the values r S + h (r < 8, h < 2) read by the sixteen lanes
+// of a point fall in sixteen distinct value slots modulo 16, if the slabs and
+// the point slots of a workgroup then fit in LDS; X2 otherwise.
+int slab_row_stride(const Plan &p) {
+  const size_t cb = p.prec == SGL_F64 ? 16 : 8;
+  const int s = p.X[2] + ((2 - p.X[2] % 4) + 4) % 4;
+  const size_t slots = (size_t)(kSlabThreads / 16) * (3 * 2 * p.q + 32) * (cb / 2);
+  return (size_t)kSlab * p.X[1] * s * cb + slots <= (size_t)kLdsMax ? s : p.X[2];
+}
+
 Geom make_geom(const Plan &p) {
   Geom g;
   g.q = p.q;
   g.S01 = box_plane_stride(p);
+  g.SR = slab_row_stride(p);
   for (int j = 0; j < 3; ++j) {
     g.N[j] = p.N[j];
     g.E[j] = p.E[j];
@@ -1743,7 +1806,8 @@ hipError_t gather_q(const Plan &p, const void *grid, void *f) {
     k_gather_tiled<R, Q2><<<(unsigned)p.nchunks, nthreads, lds, p.stream>>>(
         (const cplx<R> *)grid, (const PointRec<R> *)p.pts, p.perm, p.chunks, g, inv2lam, (cplx<R> *)f);
   } else {
-    const size_t lds = (size_t)kSlab * p.X[1] * p.X[2] * sizeof(cplx<R>);
+    if (kSlab * p.X[1] * p.X[2] >= kGatherBoxMax) return hipErrorInvalidValue;
+    const size_t lds = (size_t)kSlab * p.X[1] * g.SR * sizeof(cplx<R>) + GatherSlab<Q2>::template slot_bytes<R>();
     k_gather_slab<R, Q2><<<(unsigned)p.nchunks, kSlabThreads, lds, p.stream>>>(
         (const cplx<R> *)grid, (const PointRec<R> *)p.pts, p.perm, p.chunks, g, inv2lam, (cplx<R> *)f);
   }
