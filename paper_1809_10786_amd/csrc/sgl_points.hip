@@ -58,6 +58,7 @@ struct PrepGeom {
   double rho;
   int N[3];
   int L[3], T[3];
+  int nlo2;  // cells l2 < nlo2 come first in a dimension-0 slab of a tile (0: plain order)
 };
 
 // x~ of eq. x_tilde; t0 = arccos((2r - rho)/rho) written as
@@ -103,7 +104,13 @@ __global__ __launch_bounds__(256) void k_prep(const T *__restrict__ xyz, int64_t
   }
   pr.cell = pack_cell(b[0], b[1], b[2]);
   const uint32_t tile = (uint32_t)(((b[0] / g.L[0]) * g.T[1] + b[1] / g.L[1]) * g.T[2] + b[2] / g.L[2]);
-  const uint32_t local = (uint32_t)(((b[0] % g.L[0]) * g.L[1] + b[1] % g.L[1]) * g.L[2] + b[2] % g.L[2]);
+  // order inside a tile: dimension-0 slabs, and inside a slab the cells with
+  // l2 < nlo2 before the others, each class in (l1, l2) order (a bijection
+  // onto the tile's cells)
+  const int l0 = b[0] % g.L[0], l1 = b[1] % g.L[1], l2 = b[2] % g.L[2];
+  const int nlo = g.nlo2, nhi = g.L[2] - g.nlo2;
+  const int in_slab = nlo == 0 ? l1 * g.L[2] + l2 : (l2 < nlo ? l1 * nlo + l2 : g.L[1] * nlo + l1 * nhi + (l2 - nlo));
+  const uint32_t local = (uint32_t)(l0 * g.L[1] * g.L[2] + in_slab);
   keys[i] = tile * (uint32_t)(g.L[0] * g.L[1] * g.L[2]) + local;
   idx[i] = (int32_t)i;
   rec[i] = pr;
@@ -157,6 +164,12 @@ hipError_t launch_point_prep(Plan &p, const void *xyz, uint32_t *keys, int32_t *
     g.L[j] = p.L[j];
     g.T[j] = p.T[j];
   }
+  // The FP64 matrix-core scatter multiplies, per step of four consecutive
+  // points, the column blocks below 2 (max o2 + 2q) / 16: with the points whose
+  // dimension-2 offset in the tile stays at or below 16 - 2q grouped first,
+  // most steps of that class need one column block fewer.
+  const int thr = 16 - 2 * p.q;
+  g.nlo2 = (p.mfma64 && thr >= 0 && thr + 1 < p.L[2]) ? thr + 1 : 0;
   const int nb = (int)((p.M + 255) / 256);
   double *tout = (double *)p.ptsxyz;
   if (p.prec == SGL_F64)
