@@ -11,11 +11,12 @@
 // dimension 2 the whole period (stored index l mod N).
 //
 //  * gather (tiled): one workgroup per chunk of points of one tile of base
-//    cells; the tile's window box is staged in LDS and each thread evaluates
-//    one point at a time.
+//    cells; the tile's window box is staged in LDS and sixteen lanes (one LDS
+//    pass group) evaluate a point together.
 //  * gather (slabs): for windows too wide for the whole box in LDS, the box
 //    of a chunk's tile is streamed through LDS a few dimension-0 planes at a
-//    time, the points' partial sums kept in registers.
+//    time, sixteen lanes per point, the points' partial sums kept in
+//    registers.
 //  * scatter (tiled): one workgroup per chunk accumulates all taps of its
 //    points into the tile's window box, held as register rows, and writes the
 //    box to a staging slot of its own; a fold pass then sums, for every stored
@@ -29,7 +30,9 @@
 //  * FP32 plans with tiles of 8^3 cells use the matrix-core forms instead
 //    (k_gather_mfma, k_spread_mfma): the dimension-2 contraction of the gather
 //    and the contraction over the points of the scatter run as FP16 hi/lo
-//    products with FP32 accumulation; the staging and fold are shared.
+//    products with FP32 accumulation; the staging and fold are shared.  FP64
+//    plans with 8^3 tiles (q <= 6) scatter on the FP64 matrix cores
+//    (k_spread_mfma64), with exact FP64 products.
 #include <type_traits>
 
 #include "sgl_internal.h"
