@@ -207,12 +207,24 @@ __global__ __launch_bounds__(GatherTiled<Q2>::threads) void k_gather_tiled(const
 #pragma unroll
       for (int j1 = 0; j1 < J; ++j1) {
         const cplx<R> *row = plane + min(b + 4 * j1, Q2 - 1) * X2;
+        // the reads of half a row are issued before their products, so their
+        // LDS latencies overlap (the compiler otherwise keeps one to three in
+        // flight; a whole row in flight needs more registers than 16 waves have)
+        constexpr int H2 = (Q2 + 1) / 2;
         R cr = 0, ci = 0;
 #pragma unroll
-        for (int t2 = 0; t2 < Q2; ++t2) {
-          const cplx<R> v = row[t2];
-          cr += w2[t2] * v.re;
-          ci += w2[t2] * v.im;
+        for (int h = 0; h < Q2; h += H2) {
+          cplx<R> v[H2];
+#pragma unroll
+          for (int u = 0; u < H2; ++u) v[u] = h + u < Q2 ? row[h + u] : cplx<R>{0, 0};
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int u = 0; u < H2; ++u) {
+            if (h + u < Q2) {
+              cr += w2[h + u] * v[u].re;
+              ci += w2[h + u] * v[u].im;
+            }
+          }
         }
         br += w1[j1] * cr;
         bi += w1[j1] * ci;
