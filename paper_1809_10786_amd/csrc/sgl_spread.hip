@@ -281,8 +281,10 @@ struct GatherShape {
   static constexpr int NR = nrb * 16;
   // Row stride of the planes in halves.  An MFMA row reads kPlaneK slots; the
   // slots past X belong to the next row (or the pad after the last plane), and
-  // they meet zero weights.  20 halves (40 bytes) keeps the 16 rows of one read
-  // on distinct banks.
+  // they meet zero weights.  20 halves (40 bytes) puts the 16 rows of one read
+  // on distinct banks for lanes 0..15; the lanes gfx950 serves together in one
+  // pass of 16-byte reads (quads of even or odd index parity) still meet in a
+  // few banks (about 0.9 conflict cycles per LDS instruction, measured).
   static constexpr int KS = X <= 20 ? 20 : 24;
   static constexpr int S = ((X1p / 4) % 2 == 0) ? X1p + 4 : X1p;  // w1 floats per point: odd multiple of 4
   // Planes hold nrow rows each.  The last row block reads NR - nrow rows past a
@@ -1369,8 +1371,9 @@ __global__ __launch_bounds__(512) void k_spread_rows(const cplx<R> *__restrict__
 // are loaded while the current one is multiplied.
 constexpr int kSpreadThreads = 256;  // 4 waves
 constexpr int kSB = 128;             // points staged at once
-constexpr int kTS = kSB + 4;         // floats per weight-table row (conflict-free b128 reads)
-constexpr int kBS = kSB + 8;         // halves per B-plane column (conflict-free b128 reads)
+constexpr int kTS = kSB + 4;         // floats per weight-table row
+constexpr int kBS = kSB + 8;         // halves per B-plane column (one collision per 16-byte
+                                     // pass group; 144 clears it, with no measurable gain)
 constexpr int kNoExp = -200;         // running exponent before the first nonzero sample
 
 
