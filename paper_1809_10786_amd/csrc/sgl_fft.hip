@@ -264,9 +264,18 @@ constexpr int p2_lines() {
   return w;
 }
 
+// Threads per workgroup.  A strided pass gets two threads per radix-8
+// butterfly of a stage (256 to 1024): with at most two workgroups per compute
+// unit its row-segment loads and stores need the extra waves in flight
+// (measured on the B = 64 FP64 passes: L = 512 from 49-53 us at 256 threads to
+// 38-41 at 1024, L = 256 from 36-40 at 256 to 33-35 at 512).  A contiguous
+// pass keeps 256, which lets more of its small workgroups share a compute
+// unit (512 threads measured 2-4% slower).
 template <class R, int LOG2L, bool STRIDED>
 constexpr int p2_threads() {
-  return ((1 << LOG2L) / 8) * p2_lines<R, LOG2L, STRIDED>() >= 1024 ? 512 : 256;
+  constexpr int nb = ((1 << LOG2L) / 8) * p2_lines<R, LOG2L, STRIDED>();  // radix-8 butterflies per stage
+  if constexpr (STRIDED) return 2 * nb > 1024 ? 1024 : (2 * nb < 256 ? 256 : 2 * nb);
+  return nb >= 1024 ? 512 : 256;
 }
 
 // One in-place Stockham stage of radix RAD after NS points (NS = product of
