@@ -154,7 +154,7 @@ __device__ inline double dc_elem(const double *dc, int axis, int i, int n0, int 
 // in FP64 (the grid's values span many orders of magnitude towards r = rho and
 // an FP32 transform leaves errors of the size of the largest ones everywhere).
 template <class Ri, class Ro>
-__global__ __launch_bounds__(256) void k_fft(const cplx<Ri> *__restrict__ in, cplx<Ro> *__restrict__ out, FftPass fp,
+__global__ __launch_bounds__(512) void k_fft(const cplx<Ri> *__restrict__ in, cplx<Ro> *__restrict__ out, FftPass fp,
                                              const cplx<double> *__restrict__ tw64, const double *__restrict__ dc,
                                              int dcmode, int n0, int n1, int n2) {
   using R = double;
@@ -451,7 +451,9 @@ hipError_t fft_typed(const Plan &p, const FftPass &fp, const void *in, void *out
   if (done) return e;
   const int groups = fp.inner > 1 ? fp.outer * ((fp.inner + fp.W - 1) / fp.W) : (fp.outer + fp.W - 1) / fp.W;
   const size_t lds = (2 * (size_t)fp.L * fp.W + fp.L) * sizeof(cplx<double>);
-  k_fft<Ri, Ro><<<groups, 256, lds, p.stream>>>((const cplx<Ri> *)in, (cplx<Ro> *)out, fp,
+  // strided passes take 512 threads, as in k_fft_p2: more waves in flight for
+  // their row-segment loads and stores
+  k_fft<Ri, Ro><<<groups, fp.inner > 1 ? 512 : 256, lds, p.stream>>>((const cplx<Ri> *)in, (cplx<Ro> *)out, fp,
                                                 (const cplx<double> *)p.twiddle + p.tw_off[tw_index],
                                                 (const double *)p.deconv, dcmode, p.n[0], p.n[1], p.n[2]);
   return hipGetLastError();
