@@ -190,11 +190,20 @@ __global__ __launch_bounds__(256) void k_conv_f64(int B, const int32_t *__restri
   const bool ncol = n < N;
   const double *arow = tab + G.plane_off + (int64_t)(mt * 16 + c) * G.Kpad;
   double4_t acc = {0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < K; k0 += 4) {
-    const int k = k0 + kk;
-    const double a = arow[k];  // zero padded to Kpad >= K
-    const double b = (ncol && k < K) ? P.load(in, k, n) : 0.0;
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+  // eight K steps per round, their loads issued together (one memory latency
+  // per round instead of per step).  The table operand is zero padded to
+  // Kpad, a multiple of 32, so every a is in range; b is zero past K, and the
+  // padded steps add exact zeros to the same sums in the same order.
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    double a[8], b[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int k = k0 + 4 * u + kk;
+      a[u] = arow[k];
+      b[u] = (ncol && k < K) ? P.load(in, k, n) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
   }
   if (!ncol) return;
 #pragma unroll
