@@ -4,7 +4,7 @@
 // cell and a fractional offset, and binning of the points into tiles of base
 // cells (a stable radix sort on the tile-major cell key).
 #include <cstring>
-#include <rocprim/device/device_radix_sort.hpp>
+#include <utility>
 
 #include "sgl_internal.h"
 
@@ -146,6 +146,158 @@ __global__ __launch_bounds__(256) void k_tile_bounds(const uint32_t *__restrict_
   tile_start[t] = (int32_t)lo;
 }
 
+
+// ---------------------------------------------------------------- point sort
+
+// Stable least-significant-digit radix sort of (key, index) pairs with digits
+// of at most 8 bits.  A pass counts the digits of every tile of kSortTile
+// consecutive elements, scans the counts digit-major (digit 0 of every tile,
+// then digit 1, ...), and moves each element to its digit's scanned offset
+// for its tile plus its rank among the tile's earlier elements of the same
+// digit.  Ranks and counts come from wave ballots over the lanes holding the
+// same digit, so nothing is atomic: equal keys keep their input order and the
+// permutation is the same on every run.
+constexpr int kSortThreads = 256;
+constexpr int kSortWaves = kSortThreads / 64;
+constexpr int kSortItems = 16;                          // elements per thread and pass
+constexpr int kSortTile = kSortThreads * kSortItems;    // elements per workgroup
+constexpr int kSortRadix = 256;                         // counters per tile (8-bit digits)
+constexpr int kScanChunk = 4 * kSortThreads;            // counters per workgroup of the scan
+static_assert(kSortThreads == kSortRadix, "one thread per digit in the per-digit steps");
+
+// Lanes of the wave whose element is valid and has digit d (bits wide).
+__device__ inline uint64_t digit_peers(uint32_t d, bool valid, int bits) {
+  uint64_t m = __ballot(valid);
+  for (int b = 0; b < bits; ++b) {
+    const bool set = (d >> b) & 1u;
+    const uint64_t v = __ballot(set);
+    m &= set ? v : ~v;
+  }
+  return m;
+}
+
+// counts[d * ntile + tile] = number of elements of the tile with digit d
+__global__ __launch_bounds__(kSortThreads) void k_sort_count(const uint32_t *__restrict__ keys, int64_t M,
+                                                             int shift, int bits, int ntile,
+                                                             uint32_t *__restrict__ counts) {
+  __shared__ uint32_t wc[kSortWaves][kSortRadix];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int e = threadIdx.x; e < kSortWaves * kSortRadix; e += kSortThreads) (&wc[0][0])[e] = 0;
+  __syncthreads();
+  const uint32_t mask = (1u << bits) - 1u;
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  for (int s = 0; s < kSortItems; ++s) {
+    const int64_t i = base + (int64_t)s * kSortThreads + threadIdx.x;
+    const bool valid = i < M;
+    const uint32_t d = valid ? (keys[i] >> shift) & mask : 0u;
+    const uint64_t m = digit_peers(d, valid, bits);
+    // the highest lane of each digit group adds the group's size
+    if (valid && (m >> lane) == 1ull) wc[wave][d] += (uint32_t)__popcll(m);
+  }
+  __syncthreads();
+  uint32_t t = 0;
+  for (int w = 0; w < kSortWaves; ++w) t += wc[w][threadIdx.x];
+  counts[(int64_t)threadIdx.x * ntile + blockIdx.x] = t;
+}
+
+// Exclusive scan of x over the workgroup; *total gets the sum of all x.
+__device__ inline uint32_t block_exclusive_scan(uint32_t x, uint32_t *wsum, uint32_t *total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t inc = x;
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t t = __shfl_up(inc, off, 64);
+    if (lane >= off) inc += t;
+  }
+  if (lane == 63) wsum[wave] = inc;
+  __syncthreads();
+  uint32_t before = 0, all = 0;
+  for (int w = 0; w < kSortWaves; ++w) {
+    if (w < wave) before += wsum[w];
+    all += wsum[w];
+  }
+  __syncthreads();  // wsum is free again
+  *total = all;
+  return before + inc - x;
+}
+
+// a[i0 .. i0 + kScanChunk) replaced by its exclusive scan plus carry; returns
+// the chunk's sum
+__device__ inline uint32_t scan_chunk(uint32_t *a, int64_t n, int64_t i0, uint32_t carry, uint32_t *wsum) {
+  const int64_t j = i0 + 4 * (int64_t)threadIdx.x;
+  uint32_t v[4], sum = 0;
+  for (int u = 0; u < 4; ++u) {
+    v[u] = j + u < n ? a[j + u] : 0u;
+    sum += v[u];
+  }
+  uint32_t total;
+  uint32_t run = carry + block_exclusive_scan(sum, wsum, &total);
+  for (int u = 0; u < 4; ++u) {
+    if (j + u < n) a[j + u] = run;
+    run += v[u];
+  }
+  return total;
+}
+
+// each chunk of kScanChunk counters scanned on its own; its sum to sums[chunk]
+__global__ __launch_bounds__(kSortThreads) void k_scan_chunks(uint32_t *__restrict__ a, int64_t n,
+                                                              uint32_t *__restrict__ sums) {
+  __shared__ uint32_t wsum[kSortWaves];
+  const uint32_t total = scan_chunk(a, n, (int64_t)blockIdx.x * kScanChunk, 0u, wsum);
+  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+// the chunk sums scanned by one workgroup, strip by strip
+__global__ __launch_bounds__(kSortThreads) void k_scan_sums(uint32_t *__restrict__ sums, int64_t nchunk) {
+  __shared__ uint32_t wsum[kSortWaves];
+  uint32_t carry = 0;
+  for (int64_t i0 = 0; i0 < nchunk; i0 += kScanChunk) carry += scan_chunk(sums, nchunk, i0, carry, wsum);
+}
+
+// One pass: element i of tile b with digit d goes to
+// offs[d * ntile + b] + sums[(d * ntile + b) / kScanChunk] + (its rank in the tile).
+__global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
+    const uint32_t *__restrict__ kin, const int32_t *__restrict__ vin, int64_t M, int shift, int bits, int ntile,
+    const uint32_t *__restrict__ offs, const uint32_t *__restrict__ sums, uint32_t *__restrict__ kout,
+    int32_t *__restrict__ vout) {
+  __shared__ uint32_t next[kSortRadix];            // output position of the tile's next element of each digit
+  __shared__ uint32_t wc[kSortWaves][kSortRadix];  // this round's count per wave and digit
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  {
+    const int64_t j = (int64_t)threadIdx.x * ntile + blockIdx.x;
+    next[threadIdx.x] = offs[j] + sums[j / kScanChunk];
+  }
+  for (int e = threadIdx.x; e < kSortWaves * kSortRadix; e += kSortThreads) (&wc[0][0])[e] = 0;
+  __syncthreads();
+  const uint32_t mask = (1u << bits) - 1u;
+  const uint64_t below = (1ull << lane) - 1ull;
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  for (int s = 0; s < kSortItems; ++s) {
+    // round s holds the tile's elements s * kSortThreads .. + kSortThreads - 1 in thread order
+    const int64_t i = base + (int64_t)s * kSortThreads + threadIdx.x;
+    const bool valid = i < M;
+    const uint32_t k = valid ? kin[i] : 0u;
+    const int32_t v = valid ? vin[i] : 0;
+    const uint32_t d = (k >> shift) & mask;
+    const uint64_t m = digit_peers(d, valid, bits);
+    if (valid && (m >> lane) == 1ull) wc[wave][d] = (uint32_t)__popcll(m);
+    __syncthreads();
+    if (valid) {
+      uint32_t pos = next[d] + (uint32_t)__popcll(m & below);
+      for (int w = 0; w < wave; ++w) pos += wc[w][d];
+      kout[pos] = k;
+      vout[pos] = v;
+    }
+    __syncthreads();
+    uint32_t t = 0;
+    for (int w = 0; w < kSortWaves; ++w) {
+      t += wc[w][threadIdx.x];
+      wc[w][threadIdx.x] = 0;
+    }
+    next[threadIdx.x] += t;
+    __syncthreads();
+  }
+}
+
 }  // namespace
 
 hipError_t launch_point_radius(const Plan &p, const void *xyz, double *partial, int nblocks) {
@@ -182,19 +334,36 @@ hipError_t launch_point_prep(Plan &p, const void *xyz, uint32_t *keys, int32_t *
 }
 
 // Sort (key, index) pairs, permute the point records into sorted order and
-// find the tile boundaries.  keys/idx hold 2*M entries (input and output halves).
+// find the tile boundaries.  keys holds 2*M entries (input and output halves),
+// idx M input indices; the sorted indices go to p.perm.
 hipError_t launch_point_sort(Plan &p, uint32_t *keys, int32_t *idx, void *unsorted) {
-  const size_t M = (size_t)p.M;
-  uint32_t key_bits = 1;
+  const int64_t M = p.M;
+  int key_bits = 1;
   const uint64_t maxkey = (uint64_t)p.ntiles * p.L[0] * p.L[1] * p.L[2];
   while (key_bits < 32 && (1ull << key_bits) < maxkey) ++key_bits;
-  size_t tmp_bytes = 0;
-  hipError_t e = rocprim::radix_sort_pairs(nullptr, tmp_bytes, keys, keys + M, idx, p.perm, M, 0, key_bits, p.stream);
+  // an odd number of passes, so that the last one writes keys + M and p.perm
+  const int npass = key_bits <= 8 ? 1 : (key_bits <= 24 ? 3 : 5);
+  const int bits = (key_bits + npass - 1) / npass;
+  const int ntile = (int)((M + kSortTile - 1) / kSortTile);
+  const int64_t ncount = (int64_t)kSortRadix * ntile;
+  const int64_t nchunk = (ncount + kScanChunk - 1) / kScanChunk;
+  uint32_t *counts = nullptr;
+  hipError_t e = hipMalloc(&counts, (size_t)(ncount + nchunk) * sizeof(uint32_t));
   if (e != hipSuccess) return e;
-  void *tmp = nullptr;
-  e = hipMalloc(&tmp, tmp_bytes ? tmp_bytes : 16);
-  if (e != hipSuccess) return e;
-  e = rocprim::radix_sort_pairs(tmp, tmp_bytes, keys, keys + M, idx, p.perm, M, 0, key_bits, p.stream);
+  uint32_t *sums = counts + ncount;
+  uint32_t *kin = keys, *kout = keys + M;
+  int32_t *vin = idx, *vout = p.perm;
+  for (int pass = 0; pass < npass && e == hipSuccess; ++pass) {
+    const int shift = pass * bits;
+    k_sort_count<<<ntile, kSortThreads, 0, p.stream>>>(kin, M, shift, bits, ntile, counts);
+    k_scan_chunks<<<(unsigned)nchunk, kSortThreads, 0, p.stream>>>(counts, ncount, sums);
+    k_scan_sums<<<1, kSortThreads, 0, p.stream>>>(sums, nchunk);
+    k_sort_scatter<<<ntile, kSortThreads, 0, p.stream>>>(kin, vin, M, shift, bits, ntile, counts, sums, kout, vout);
+    e = hipGetLastError();
+    std::swap(kin, kout);
+    std::swap(vin, vout);
+  }
+  // kin / vin now name keys + M and p.perm
   if (e == hipSuccess) {
     const int nb = (int)((M + 255) / 256);
     if (p.prec == SGL_F64)
@@ -212,7 +381,7 @@ hipError_t launch_point_sort(Plan &p, uint32_t *keys, int32_t *idx, void *unsort
     e = hipGetLastError();
   }
   const hipError_t es = hipStreamSynchronize(p.stream);
-  hipFree(tmp);
+  hipFree(counts);
   return e != hipSuccess ? e : es;
 }
 

@@ -256,6 +256,24 @@ def test_gather_is_deterministic():
     assert np.array_equal(a, b)
 
 
+def test_point_binning_is_deterministic():
+    """Plan-time binning is a stable sort: two plans over the same points, with
+    many equal cell keys spread over several sort tiles and a ragged tail,
+    give bit-identical adjoints (sums over the points of a cell in the same
+    order), and the adjoint stays within the NFFT tolerance of the direct sum."""
+    B = 12
+    base = wl.gaussian_points(20_000, 21)
+    # 60 positions repeated 200 times each (equal keys), shuffled among the rest
+    pts = np.concatenate([np.repeat(base[:60], 200, axis=0), base[60:]])
+    pts = pts[np.random.default_rng(22).permutation(len(pts))]
+    y = wl.samples(len(pts), 23)
+    say("binning determinism:", len(pts), "points")
+    g1 = host(plan(pts, B, q=8).adjoint(dev(y, torch.complex128)))
+    g2 = host(plan(pts, B, q=8).adjoint(dev(y, torch.complex128)))
+    assert np.array_equal(g1, g2), "two plans over the same points differ"
+    assert rel(g1, oracle.direct_adjoint(B, pts, y)) < 1e-7
+
+
 # ------------------------------------------------------------ edge cases
 
 
