@@ -190,8 +190,8 @@ __global__ __launch_bounds__(256) void k_conv_f64(int B, const int32_t *__restri
   const bool ncol = n < N;
   const double *arow = tab + G.plane_off + (int64_t)(mt * 16 + c) * G.Kpad;
   double4_t acc = {0.0, 0.0, 0.0, 0.0};
-  // eight K steps per round, their loads issued together (one memory latency
-  // per round instead of per step).  The table operand is zero padded to
+  // eight K steps per batch, their loads issued together (one memory latency
+  // per batch instead of per step).  The table operand is zero padded to
   // Kpad, a multiple of 32, so every a is in range; b is zero past K, and the
   // padded steps add exact zeros to the same sums in the same order.
   for (int k0 = 0; k0 < K; k0 += 32) {

@@ -260,7 +260,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
     const uint32_t *__restrict__ offs, const uint32_t *__restrict__ sums, uint32_t *__restrict__ kout,
     int32_t *__restrict__ vout) {
   __shared__ uint32_t next[kSortRadix];            // output position of the tile's next element of each digit
-  __shared__ uint32_t wc[kSortWaves][kSortRadix];  // this round's count per wave and digit
+  __shared__ uint32_t wc[kSortWaves][kSortRadix];  // this sweep's count per wave and digit
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   {
     const int64_t j = (int64_t)threadIdx.x * ntile + blockIdx.x;
@@ -272,7 +272,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
   const uint64_t below = (1ull << lane) - 1ull;
   const int64_t base = (int64_t)blockIdx.x * kSortTile;
   for (int s = 0; s < kSortItems; ++s) {
-    // round s holds the tile's elements s * kSortThreads .. + kSortThreads - 1 in thread order
+    // sweep s holds the tile's elements s * kSortThreads .. + kSortThreads - 1 in thread order
     const int64_t i = base + (int64_t)s * kSortThreads + threadIdx.x;
     const bool valid = i < M;
     const uint32_t k = valid ? kin[i] : 0u;
